@@ -1,0 +1,28 @@
+"""Builds the FP64 oracle library (oracle/libpfo.so) with gcc.
+
+Flags: -O2 -ffp-contract=off (no fused multiply-add contraction), no
+fast-math, so the library evaluates every expression as written in IEEE
+binary64 with round-to-nearest-even.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libpfo.so")
+
+
+def build(verbose: bool = False) -> str:
+    src = os.path.join(HERE, "pfo.c")
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall", "-Wextra",
+           "-fPIC", "-shared", src, "-o", LIB + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,286 @@
+"""Seeded synthetic inputs shared by the HIP path and the FP64 oracle.
+
+This module holds only case definitions and random draws: the SplitMix64
+stream, the tanh bubble profile used as the initial phase field
+(Sec. 4.2, Eq. (42)), velocity noise, and the parameter presets of the
+benchmark workloads.  It contains none of the lattice Boltzmann arithmetic
+and imports neither the oracle nor the HIP binding; both sides receive the
+identical host arrays produced here.
+
+Coordinates: node (x, y) sits at integer position (x, y), x in [0, nx) is
+periodic, y in [0, ny) is bounded by walls at y = -1/2 and y = ny - 1/2.
+Fields are float64 arrays of shape (ny, nx) (row-major, x fastest).
+"""
+from __future__ import annotations
+
+import copy
+import numpy as np
+
+_MASK = (1 << 64) - 1
+_GAMMA = 0x9E3779B97F4A7C15
+
+
+def splitmix64(seed: int, n: int, offset: int = 0) -> np.ndarray:
+    """Draws offset+1 .. offset+n of the SplitMix64 stream seeded with `seed`.
+
+    SplitMix64 (Steele, Lea, Flood 2014): state advances by the golden gamma,
+    output is the variant-13 mix of the state.  Counter-based form: draw k is
+    mix(seed + k*gamma), so any slice can be generated independently.
+    """
+    k = np.arange(offset + 1, offset + n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & _MASK) + k * np.uint64(_GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform(seed: int, n: int, lo: float = 0.0, hi: float = 1.0, offset: int = 0) -> np.ndarray:
+    """n doubles in [lo, hi) from the top 53 bits of SplitMix64 draws."""
+    u = (splitmix64(seed, n, offset) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    return lo + (hi - lo) * u
+
+
+def bubble_field(nx: int, ny: int, bubbles, xi: float) -> np.ndarray:
+    """Dispersed-phase concentration of circular bubbles with a tanh rim.
+
+    Each bubble (cx, cy, R) contributes 0.5 - 0.5 tanh((r - R) / (xi/2)),
+    the initial condition of Sec. 4.2 (Eq. (42)) with d_b = 2R.  Distances
+    use the minimum image in the periodic x direction.  Contributions of
+    separate bubbles are added and the sum is capped at 1.
+    """
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    c = np.zeros((ny, nx))
+    for (cx, cy, r) in bubbles:
+        dx = x - cx
+        dx = dx - nx * np.round(dx / nx)
+        dist = np.sqrt(dx * dx + (y - cy) ** 2)
+        c += 0.5 - 0.5 * np.tanh((dist - r) / (0.5 * xi))
+    return np.minimum(c, 1.0)
+
+
+def velocity_noise(nx: int, ny: int, seed: int, amp: float):
+    """i.i.d. U[-amp, amp) noise for u_x then u_y, shape (2, ny, nx)."""
+    v = uniform(seed, 2 * nx * ny, -amp, amp)
+    return v.reshape(2, ny, nx)
+
+
+def default_params(nx: int, ny: int) -> dict:
+    """Parameter block with the ABI's field names (two-phase, Newtonian)."""
+    return dict(
+        nx=nx, ny=ny, n_h=1,
+        rho=[1e-3, 1e-3, 1.0],       # rho_1 (gas), rho_2 (unused when n_h=1), rho_3 (liquid)
+        nu=[1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0],
+        powerlaw_comp=-1,            # component whose viscosity follows the power law, or -1
+        K=0.1, n=1.0, nu_min=1e-4, nu_max=1.0,
+        sigma12=1e-3, sigma13=1e-3, sigma23=1e-3, Lambda=0.0,
+        xi=4.0, D0=4.0 / 300.0, variable_mobility=1,
+        tau_h=0.5, g=0.0, fx=0.0,
+        storage=0, store_h=0,
+    )
+
+
+def gravity_from_eotvos(eo: float, sigma: float, rho_l: float, rho_g: float, d: float) -> float:
+    """g such that Eo = (rho_l - rho_g) g d^2 / sigma (Sec. 4.1, Eq. (40))."""
+    return eo * sigma / ((rho_l - rho_g) * d * d)
+
+
+def _case(params, C, u=None, p=None, name=""):
+    return dict(name=name, params=params, C=np.ascontiguousarray(C, dtype=np.float64),
+                u=None if u is None else np.ascontiguousarray(u, dtype=np.float64),
+                p=None if p is None else np.ascontiguousarray(p, dtype=np.float64))
+
+
+def hydrostatic_pressure(C, params: dict) -> np.ndarray:
+    """Initial pressure in hydrostatic balance with F_b = -rho g j along each
+    column: p(y) - p(y+1) = g (rho(y) + rho(y+1)) / 2 from the top row down,
+    shifted to zero mean.  rho = sum_k rho_k C_k with each C_k limited to
+    [0, 1].  Starting from p = 0 instead launches a pressure transient that a
+    density ratio of 1000 does not survive."""
+    C = np.asarray(C, dtype=np.float64)
+    c1 = C[0]
+    c2 = C[1] if C.shape[0] > 1 else np.zeros_like(c1)
+    r = params["rho"]
+    rho = (r[0] * np.clip(c1, 0, 1) + r[1] * np.clip(c2, 0, 1) + r[2] * np.clip(1 - c1 - c2, 0, 1))
+    g = float(params["g"])
+    p = np.zeros_like(rho)
+    for y in range(rho.shape[0] - 2, -1, -1):
+        p[y] = p[y + 1] + g * 0.5 * (rho[y] + rho[y + 1])
+    return p - p.mean()
+
+
+def gravity_for_gas_mach(radius: float, density_ratio: float, mach: float = 0.01) -> float:
+    """g whose buoyant acceleration of the gas, (rho_l/rho_g) g, reaches the
+    velocity mach * c_s within one acoustic crossing R / c_s of the bubble."""
+    cs = 1.0 / np.sqrt(3.0)
+    return mach * cs * cs / (density_ratio * radius)
+
+
+def rising_bubble_small(seed: int = 1, nx: int = 64, ny: int = 128, density_ratio: float = 100.0) -> dict:
+    """Two-phase rising bubble, 64x128: R=8 at (32,32), xi=4, Newtonian
+    liquid with tau_l = 0.8 (nu_l = 0.8/3), dynamic viscosity ratio 100
+    (nu_g = 10 nu_l at density ratio 1000, kept at the lower density ratio),
+    constant mobility scale 0.02, sigma = 1e-3, g from Eo = 10, velocity noise
+    +-1e-4 and a hydrostatic initial pressure.  A bubble this small is stable
+    at density ratio 100 with this scheme, not at 1000."""
+    prm = default_params(nx, ny)
+    nu_l = 0.8 / 3.0
+    nu_g = 10.0 * nu_l
+    rg = 1.0 / density_ratio
+    prm.update(rho=[rg, rg, 1.0], nu=[nu_g, nu_g, nu_l], powerlaw_comp=-1, n=1.0,
+               D0=0.02, variable_mobility=0,
+               g=gravity_from_eotvos(10.0, 1e-3, 1.0, rg, 16.0))
+    C = bubble_field(nx, ny, [(nx / 2.0, ny / 4.0, 8.0)], prm["xi"])[None]
+    u = velocity_noise(nx, ny, seed, 1e-4)
+    return _case(prm, C, u, hydrostatic_pressure(C, prm), f"rising_bubble_{nx}x{ny}")
+
+
+def static_bubble(nx: int = 96, ny: int = 96, radius: float = 25.0, density_ratio: float = 1000.0,
+                  sigma: float = 1e-4, variable_mobility: int = 0) -> dict:
+    """Bubble at rest in the middle of the box, no gravity."""
+    prm = default_params(nx, ny)
+    rg = 1.0 / density_ratio
+    prm.update(rho=[rg, rg, 1.0], nu=[1.0 / 6.0] * 3, sigma12=sigma, sigma13=sigma, sigma23=sigma,
+               variable_mobility=variable_mobility, g=0.0)
+    C = bubble_field(nx, ny, [(nx / 2.0, ny / 2.0, radius)], prm["xi"])[None]
+    return _case(prm, C, None, None, f"static_bubble_{nx}x{ny}_R{radius}")
+
+
+def powerlaw_bubble(n: float = 0.5, eo: float = 10.0, nx: int = 200, ny: int = 400, d: float = 50.0,
+                    density_ratio: float = 1000.0, K: float = 0.1, mach: float = 0.01) -> dict:
+    """Single bubble (diameter d, centre (nx/2, 0.6 nx), Eq. (42)) rising in
+    a power-law liquid, K and n given, nu in [1e-4, 1], gas nu = c_s^2 * 0.5
+    (tau_d = 0.5 as in the paper's Table 5), constant mobility xi/300,
+    g from `gravity_for_gas_mach` and sigma from Eo."""
+    prm = default_params(nx, ny)
+    rg = 1.0 / density_ratio
+    g = gravity_for_gas_mach(d / 2.0, density_ratio, mach)
+    sigma = (1.0 - rg) * g * d * d / eo
+    prm.update(rho=[rg, rg, 1.0], nu=[1.0 / 6.0, 1.0 / 6.0, 1.0], powerlaw_comp=2,
+               K=K, n=n, nu_min=1e-4, nu_max=1.0, variable_mobility=0,
+               sigma12=sigma, sigma13=sigma, sigma23=sigma, g=g)
+    C = bubble_field(nx, ny, [(nx / 2.0, 0.6 * nx, d / 2.0)], prm["xi"])[None]
+    return _case(prm, C, None, hydrostatic_pressure(C, prm), f"powerlaw_bubble_{nx}x{ny}_n{n:.3f}_Eo{eo:.2f}")
+
+
+def three_component(variable_mobility: int = 0, nx: int = 256, ny: int = 512) -> dict:
+    """Three components: C1 bubble R=40 at (128,160), C2 bubble R=25 at
+    (128,330) above it, liquid C3 power law n=0.7, K=0.1, both dispersed
+    phases rho = 1e-3, nu = 1/6, sigma_ij = 1e-4, Lambda = 0."""
+    prm = default_params(nx, ny)
+    sx, sy = nx / 256.0, ny / 512.0
+    g = gravity_for_gas_mach(40.0, 1000.0, 0.01)
+    prm.update(n_h=2, rho=[1e-3, 1e-3, 1.0], nu=[1.0 / 6.0, 1.0 / 6.0, 1.0], powerlaw_comp=2,
+               K=0.1, n=0.7, nu_min=1e-4, nu_max=1.0, variable_mobility=variable_mobility,
+               sigma12=1e-4, sigma13=1e-4, sigma23=1e-4, g=g)
+    s = min(sx, sy)
+    c1 = bubble_field(nx, ny, [(128.0 * sx, 160.0 * sy, 40.0 * s)], prm["xi"])
+    c2 = bubble_field(nx, ny, [(128.0 * sx, 330.0 * sy, 25.0 * s)], prm["xi"])
+    C = np.stack([c1, c2])
+    return _case(prm, C, None, hydrostatic_pressure(C, prm), f"three_component_{nx}x{ny}")
+
+
+def place_bubbles(nx: int, ny: int, count: int, rmin: float, rmax: float, xi: float, seed: int,
+                  max_draws: int = 200000):
+    """Rejection sampling of non-overlapping bubbles: centre gap >= R1+R2+2xi,
+    distance to each wall >= R+2xi.  Draws come from one SplitMix64 stream."""
+    out = []
+    k = 0
+    while len(out) < count:
+        if k >= max_draws:
+            raise RuntimeError("could not place bubbles")
+        r, cx, cy = uniform(seed, 3, 0.0, 1.0, offset=3 * k)
+        k += 1
+        r = rmin + (rmax - rmin) * r
+        cx = cx * nx
+        cy = r + 2 * xi + cy * (ny - 2 * (r + 2 * xi))
+        ok = True
+        for (bx, by, br) in out:
+            dx = cx - bx
+            dx -= nx * round(dx / nx)
+            if (dx * dx + (cy - by) ** 2) < (r + br + 2 * xi) ** 2:
+                ok = False
+                break
+        if ok:
+            out.append((cx, cy, r))
+    return out
+
+
+LARGE_RMIN, LARGE_RMAX = 25.0, 40.0
+
+
+def large_domain_params(nx: int = 2048, ny: int = 4096, storage: int = 0) -> dict:
+    """Power-law liquid n=0.6, K=0.1, nu in [1e-4, 1], density ratio 1000,
+    sigma = 1e-4, g from `gravity_for_gas_mach` at the largest radius."""
+    prm = default_params(nx, ny)
+    prm.update(rho=[1e-3, 1e-3, 1.0], nu=[1.0 / 6.0, 1.0 / 6.0, 1.0], powerlaw_comp=2,
+               K=0.1, n=0.6, nu_min=1e-4, nu_max=1.0, variable_mobility=0,
+               sigma12=1e-4, sigma13=1e-4, sigma23=1e-4,
+               g=gravity_for_gas_mach(LARGE_RMAX, 1000.0, 0.01), storage=storage)
+    return prm
+
+
+def many_bubbles(nx: int = 2048, ny: int = 4096, count: int = 64, seed: int = 5, storage: int = 0,
+                 with_pressure: bool = True) -> dict:
+    """Large single domain with `count` non-overlapping seeded bubbles,
+    R ~ U[25, 40], in the power-law liquid of `large_domain_params`."""
+    prm = large_domain_params(nx, ny, storage)
+    bubbles = place_bubbles(nx, ny, count, LARGE_RMIN, LARGE_RMAX, prm["xi"], seed)
+    C = bubble_field(nx, ny, bubbles, prm["xi"])[None]
+    p = hydrostatic_pressure(C, prm) if with_pressure else None
+    case = _case(prm, C, None, p, f"many_bubbles_{nx}x{ny}_{count}")
+    case["bubbles"] = bubbles
+    return case
+
+
+def many_bubbles_crop(nx: int = 2048, ny: int = 4096, count: int = 64, seed: int = 5,
+                      cw: int = 256, ch: int = 512, storage: int = 0) -> dict:
+    """A cw x ch window of `many_bubbles`, as its own domain with the same
+    physical parameters: the window is centred on the first placed bubble
+    (clamped to the domain) and keeps the bubbles lying fully inside it."""
+    prm = large_domain_params(cw, ch, storage)
+    bubbles = place_bubbles(nx, ny, count, LARGE_RMIN, LARGE_RMAX, prm["xi"], seed)
+    bx, by, _ = bubbles[0]
+    x0 = int(min(max(np.floor(bx) - cw // 2, 0), nx - cw))
+    y0 = int(min(max(np.floor(by) - ch // 2, 0), ny - ch))
+    inside = [(x - x0, y - y0, r) for (x, y, r) in bubbles
+              if x - r - prm["xi"] >= x0 and x + r + prm["xi"] < x0 + cw
+              and y - r - prm["xi"] >= y0 and y + r + prm["xi"] < y0 + ch]
+    C = bubble_field(cw, ch, inside, prm["xi"])[None]
+    case = _case(prm, C, None, hydrostatic_pressure(C, prm), f"many_bubbles_crop_{cw}x{ch}")
+    case["bubbles"] = inside
+    case["origin"] = (x0, y0)
+    return case
+
+
+def batch_sweep(count_per_size: int = 16, seed: int = 4, sizes=((150, 300), (200, 400), (300, 600))):
+    """Uneven batch: `count_per_size` cases of each size, n ~ U[0.5,1.5],
+    Eo ~ U[1,100], density ratio 1000, d = width/5."""
+    cases = []
+    k = 0
+    for (nx, ny) in sizes:
+        for _ in range(count_per_size):
+            n, eo = uniform(seed, 2, 0.0, 1.0, offset=2 * k)
+            k += 1
+            n = 0.5 + n
+            eo = 1.0 + 99.0 * eo
+            c = powerlaw_bubble(n=n, eo=eo, nx=nx, ny=ny, d=nx / 5.0)
+            c["name"] = f"batch_{nx}x{ny}_{k}"
+            cases.append(c)
+    return cases
+
+
+def channel(n: float, ny: int = 32, nx: int = 5, fx: float = 1e-6, K: float = 0.01,
+            nu_min: float = 1e-3, nu_max: float = 1.0) -> dict:
+    """Single-phase power-law liquid between walls, driven by a body force
+    along x (liquid only: C1 = 0)."""
+    prm = default_params(nx, ny)
+    prm.update(rho=[1.0, 1.0, 1.0], nu=[1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0], powerlaw_comp=2,
+               K=K, n=n, nu_min=nu_min, nu_max=nu_max, g=0.0, fx=fx)
+    C = np.zeros((1, ny, nx))
+    return _case(prm, C, None, None, f"channel_n{n}")
+
+
+def clone(case: dict) -> dict:
+    return copy.deepcopy(case)

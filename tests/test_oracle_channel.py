@@ -1,0 +1,100 @@
+"""Closed-form pin of the rheology (Sec. 2.3, Eqs. (25)-(33)) and of the
+walls: steady flow of a truncated power-law liquid between the half-way
+bounce-back walls, driven along the periodic x direction by a body force G.
+
+Stress balance gives tau_xy = -G y (y from the channel centre, half-width L
+= ny/2), so the local shear rate solves eta(gdot) gdot = G |y| with
+eta = clamp(K gdot^(n-1), nu_min, nu_max) (rho = 1) and
+u(y) = int_|y|^L gdot(s) ds.  Without truncation this is Eq. (34)'s profile
+u = n/(n+1) (G/K)^(1/n) (L^((n+1)/n) - |y|^((n+1)/n)).  The error bound is the
+paper's Table 2 (tests/golden), whose channel is the inlet/outlet variant.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle.pfo import Oracle
+from paper_2207_09431_amd import inputs
+from helpers import rel_l2
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table2_channel_erel.json")
+
+
+def shear_rate(stress, K, n, nu_min, nu_max):
+    """Solve clamp(K g^(n-1)) g = stress for g >= 0 (monotone in g)."""
+    if stress <= 0:
+        return 0.0
+    g = (stress / K) ** (1.0 / n)
+    nu = K * g ** (n - 1.0)
+    if nu > nu_max:
+        return stress / nu_max
+    if nu < nu_min:
+        return stress / nu_min
+    return g
+
+
+def analytic_profile(ny, G, K, n, nu_min, nu_max, fine=4000):
+    L = ny / 2.0
+    s = np.linspace(0.0, L, fine + 1)
+    gd = np.array([shear_rate(G * v, K, n, nu_min, nu_max) for v in s])
+    # cumulative trapezoid from the wall inwards
+    seg = 0.5 * (gd[1:] + gd[:-1]) * np.diff(s)
+    U = np.concatenate([np.cumsum(seg[::-1])[::-1], [0.0]])     # U(s) = int_s^L gdot
+    ys = np.abs(np.arange(ny) + 0.5 - L)                         # node distance from the centre
+    return np.interp(ys, s, U)
+
+
+# consistency K per index so that the apparent viscosity is of order 0.1
+K_FOR_N = {0.5: 0.0025, 0.8: 0.025, 1.0: 0.1, 1.5: 4.0}
+
+
+def run_channel(n, max_steps=60000, **sw):
+    """Advance to steady state: relative change of u over 500 steps below
+    1e-8 (the paper's criterion of Sec. 3.3, applied per 500 steps)."""
+    K, ny = K_FOR_N[n], 32
+    L = ny / 2.0
+    # body force chosen for a centre velocity of about 0.01 without truncation
+    G = K * (0.01 * (n + 1) / n / L ** ((n + 1) / n)) ** n
+    case = inputs.channel(n, ny=ny, nx=5, fx=G, K=K, nu_min=1e-3, nu_max=1.0)
+    prm = dict(case["params"]); prm.update(sw)
+    o = Oracle(prm)
+    o.init_fields(case["C"])
+    u_old = np.zeros(ny)
+    for _ in range(max_steps // 500):
+        o.step(500)
+        u = o.macroscopic()["u"][0][:, 2]
+        if np.linalg.norm(u - u_old) < 1e-8 * np.linalg.norm(u):
+            break
+        u_old = u
+    ref = analytic_profile(ny, G, K, n, 1e-3, 1.0)
+    return u, ref
+
+
+@pytest.mark.parametrize("n", [0.5, 0.8, 1.0, 1.5])
+def test_powerlaw_channel_matches_closed_form(n):
+    gold = json.load(open(GOLDEN))
+    bound = dict(zip(gold["n"], gold["E_rel"]))[n]
+    u, ref = run_channel(n)
+    err = rel_l2(u, ref)
+    assert err < bound, (n, err)
+    # the periodic body-force channel has no inlet/outlet error: far below Table 2
+    assert err < 0.005, (n, err)
+
+
+def test_untruncated_profile_is_eq34():
+    # the quadrature reproduces Eq. (34)'s closed form when no clamp is active
+    ny, K, n, G = 32, 0.01, 0.5, 2e-5
+    L = ny / 2.0
+    ref = analytic_profile(ny, G, K, n, 1e-12, 1e12, fine=200000)
+    ys = np.abs(np.arange(ny) + 0.5 - L)
+    closed = n / (n + 1) * (G / K) ** (1 / n) * (L ** ((n + 1) / n) - ys ** ((n + 1) / n))
+    assert rel_l2(ref, closed) < 1e-8
+
+
+def test_literal_strain_factor_is_rejected_by_the_closed_form():
+    # feeding Eq. (29) into Eq. (25) literally scales gdot by tau/(tau+1/2):
+    # the shear-thinning profile then misses the closed form by far more
+    u, ref = run_channel(0.5, strain_literal=1)
+    assert rel_l2(u, ref) > 0.03

@@ -1,0 +1,100 @@
+"""Pins of the oracle's time step against invariants and special cases.
+
+- Initialisation round trip: the moments of the initial populations return
+  the input u, p and C (Eqs. (16), (20), (22)-(24); the 1/2 on u.grad rho in
+  the pressure moment is what makes p come back).
+- Quiescent liquid: no force, no motion; every population stays put exactly.
+- Mass: with central differences in the hbar forcing the component mass is
+  conserved to round-off (streaming, bounce-back and the split diffusion term
+  telescope), also for the conservative variable-mobility link form; with the
+  mixed-difference forcing the drift stays at the size of its O(u^2) remainder.
+- Mirror symmetry of a bubble centred in x.
+- A three-component run with C2 = 0 reproduces the two-phase run.
+"""
+import numpy as np
+import pytest
+
+from oracle.pfo import Oracle, run_case
+from paper_2207_09431_amd import inputs
+from helpers import rel_l2
+
+
+def test_init_roundtrip_ratio_1000():
+    case = inputs.many_bubbles_crop()
+    case["u"] = inputs.velocity_noise(256, 512, 7, 1e-3)
+    o = run_case(case, 0)
+    m = o.macroscopic()
+    assert np.abs(m["u"] - case["u"]).max() < 1e-14
+    assert np.abs(m["p"] - case["p"]).max() < 1e-15
+    assert np.abs(m["phi"] - case["C"]).max() < 1e-15
+    g, h, tau = o.populations()
+    # hbar sums to C exactly up to rounding; tau at zero shear is nu_max of the liquid inside the liquid
+    assert np.abs(h.sum(axis=1) - case["C"]).max() < 1e-14
+    assert abs(tau[0, 0] - 3.0 * 1.0) < 1e-12
+
+
+def test_quiescent_liquid_is_exact_fixed_point():
+    prm = inputs.default_params(9, 7)
+    prm.update(g=0.0, fx=0.0, powerlaw_comp=2, n=0.5, K=0.1)
+    o = Oracle(prm)
+    o.init_fields(np.zeros((1, 7, 9)))
+    g0, h0, t0 = o.populations()
+    o.step(25)
+    g1, h1, t1 = o.populations()
+    m = o.macroscopic()
+    assert np.array_equal(g0, g1) and np.array_equal(h0, h1)
+    assert np.abs(m["u"]).max() == 0.0 and np.abs(m["p"]).max() == 0.0
+
+
+def mass(o, comp=0):
+    return o.centroid(comp)[0]
+
+
+@pytest.mark.parametrize("vm,flux", [(0, 0), (1, 1)])
+def test_mass_exact_with_central_hbar_forcing(vm, flux):
+    case = inputs.rising_bubble_small()
+    case["params"].update(variable_mobility=vm)
+    o = run_case(case, 0, hforce_mode=1, mobility_flux=flux)
+    m0 = mass(o)
+    o.step(60)
+    assert abs(mass(o) / m0 - 1.0) < 2e-14
+
+
+def test_mass_drift_small_with_mixed_hbar_forcing():
+    case = inputs.rising_bubble_small()
+    o = run_case(case, 0)
+    m0 = mass(o)
+    o.step(60)
+    drift = abs(mass(o) / m0 - 1.0)
+    assert drift < 1e-7
+    # and it is a real (non round-off) effect of the mixed derivative
+    assert drift > 1e-13
+
+
+def test_mirror_symmetry_in_x():
+    case = inputs.rising_bubble_small()
+    case["u"] = None
+    o = run_case(case, 120)
+    m = o.macroscopic()
+    nx = case["params"]["nx"]
+    j = (nx - np.arange(nx)) % nx          # x -> nx - x about the bubble centre nx/2
+    assert np.abs(m["phi"][0] - m["phi"][0][:, j]).max() < 1e-12
+    assert np.abs(m["u"][0] + m["u"][0][:, j]).max() < 1e-14
+    assert np.abs(m["u"][1] - m["u"][1][:, j]).max() < 1e-14
+
+
+def test_three_component_with_absent_second_phase_matches_two_phase():
+    case = inputs.rising_bubble_small()
+    o1 = run_case(case, 40)
+    prm = dict(case["params"])
+    prm["n_h"] = 2
+    C2 = np.concatenate([case["C"], np.zeros_like(case["C"])])
+    o2 = Oracle(prm)
+    o2.init_fields(C2, case["u"], case["p"])
+    o2.step(40)
+    m1, m2 = o1.macroscopic(), o2.macroscopic()
+    assert np.abs(m2["phi"][1]).max() < 1e-15   # mu_2 = 0 up to rounding of Eq. (5)
+    assert rel_l2(m2["u"], m1["u"]) < 1e-12
+    assert rel_l2(m2["phi"][0], m1["phi"][0]) < 1e-13
+    g, h, tau = o2.populations()
+    assert np.abs(h[1]).max() < 1e-15
