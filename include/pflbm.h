@@ -1,0 +1,166 @@
+/*
+ * pflbm.h -- C ABI of the MI355X (gfx950) phase-field power-law lattice
+ * Boltzmann step.
+ *
+ * Method (Ghorbanpour Arani et al., arXiv 2207.09431, Sec. 2): D2Q9
+ * pressure/momentum populations gbar (Sec. 2.2, Eqs. (12)-(16), (23)-(24))
+ * coupled to Cahn-Hilliard populations hbar^i (Eqs. (17)-(22)) of the ternary
+ * free energy (Sec. 2.1, Eqs. (1)-(7)), with a per-cell relaxation time from a
+ * truncated power-law viscosity whose shear rate comes from the
+ * non-equilibrium second moment of gbar with the previous step's tau
+ * (Sec. 2.3, Eqs. (25)-(33)).  x is periodic; the rows y = 0 and y = ny-1 are
+ * next to half-way bounce-back walls at rest.
+ *
+ * Conventions
+ *  - Every call returns a pflbm_status; no C++ exception crosses the ABI.
+ *  - Device memory is owned by the caller.  The library keeps the state in
+ *    the caller's workspace (pflbm_workspace_bytes) and allocates no device
+ *    memory; the workspace must stay valid until pflbm_destroy.  The library
+ *    owns only the host-side context.
+ *  - Work is enqueued on the HIP stream given to pflbm_create (NULL = the
+ *    null stream).  Calls are asynchronous unless stated otherwise.
+ *  - Host arrays are float64, row-major (ny, nx) with x fastest, and are
+ *    copied during the call.  Device outputs are float32, row-major (ny, nx).
+ *  - One context may be used by one host thread at a time.
+ */
+#ifndef PFLBM_H
+#define PFLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PFLBM_OK = 0,
+    PFLBM_ERR_INVALID_ARG = -1,   /* a parameter or argument is out of range */
+    PFLBM_ERR_WORKSPACE = -2,     /* workspace NULL, too small or misaligned */
+    PFLBM_ERR_DEVICE = -3,        /* a HIP call failed */
+    PFLBM_ERR_NONFINITE = -4,     /* non-finite input, or the state became non-finite */
+    PFLBM_ERR_STATE = -5,         /* call out of order (e.g. step before init_fields) */
+    PFLBM_ERR_UNSUPPORTED = -6    /* valid request this build does not provide */
+} pflbm_status;
+
+typedef struct pflbm_ctx pflbm_ctx;
+
+/*
+ * Physical and numerical parameters of one domain (one "case").
+ * Components: C1 and C2 are carried by hbar^1, hbar^2; C3 = 1 - C1 - C2
+ * (Sec. 2.1, Eq. (1)).  With n_h = 1 only C1 is carried and C2 = 0.
+ */
+typedef struct {
+    int32_t nx, ny;            /* lattice size, both >= 5 */
+    int32_t n_h;               /* 1 or 2 phase fields carried */
+    double rho[3];             /* component densities, > 0 */
+    double nu[3];              /* Newtonian kinematic viscosities nu_k = c_s^2 tau_k, > 0 */
+    int32_t powerlaw_comp;     /* component whose viscosity is the power law (0..2), or -1 */
+    double K, n;               /* power law nu_P = K gdot^(n-1) (Sec. 2.3, Eq. (31)) */
+    double nu_min, nu_max;     /* truncation of nu_P (Eq. (33)); 0 < nu_min <= nu_max */
+    double sigma12, sigma13, sigma23; /* pairwise surface tensions (Sec. 2.1) */
+    double Lambda;             /* six-fold term of the bulk free energy (Eq. (3)) */
+    double xi;                 /* interface thickness (Eq. (2)), > 0 */
+    double D0;                 /* mobility scale (Eq. (6)); xi/300 in the paper */
+    int32_t variable_mobility; /* 0: D_i = D0/Sigma_i, 1: D_i = D0/Sigma_i C_i (1-C_i) (Eq. (6)) */
+    double tau_h;              /* relaxation time of hbar (0.5 in the paper) */
+    double g;                  /* gravity: F_b = rho (fx, -g) (Eq. (12)) */
+    double fx;                 /* horizontal body acceleration (0 in the paper's bubble runs) */
+    int32_t storage;           /* 0: float32 populations, 1: float16 deviations (see below) */
+    int32_t store_h;           /* 0: keep only C_i when tau_h = 0.5 (exact), 1: store hbar */
+} pflbm_params;
+
+/*
+ * Workspace bytes for the given cases (device memory, 256-byte aligned base).
+ * Returns 0 when the parameters are invalid.
+ */
+size_t pflbm_workspace_bytes(const pflbm_params* cases, int32_t ncases);
+
+/*
+ * Creates a context for `ncases` domains (ncases = 1 is the plain path; more
+ * cases are advanced together by every launch).  All cases must share n_h,
+ * storage and store_h.  `d_workspace` is caller-owned device memory of at
+ * least pflbm_workspace_bytes(cases, ncases) bytes; `hip_stream` is a
+ * hipStream_t or NULL.  Errors: INVALID_ARG for out-of-range parameters
+ * (nx or ny < 5, n_h not 1 or 2, rho_k <= 0, nu_k <= 0, nu_min <= 0 or
+ * nu_min > nu_max, K <= 0 with a power-law component, xi <= 0, D0 < 0,
+ * tau_h <= 0, a Sigma_i <= 0, store_h = 0 with tau_h != 0.5);
+ * WORKSPACE when the workspace is NULL, small or misaligned; DEVICE when a
+ * HIP call fails.
+ */
+int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspace, size_t bytes,
+                     void* hip_stream, pflbm_ctx** out);
+
+/*
+ * Initial state of one case from host fields (Sec. 4.2: quiescent start,
+ * tanh interface of Eq. (42) supplied by the caller): C holds n_h planes,
+ * u two planes (u_x then u_y) or NULL for zero, p one plane or NULL for zero.
+ * Populations start at their equilibria (Eqs. (16), (20)) and tau at its
+ * zero-shear value.  Errors: NONFINITE for a non-finite input.
+ */
+int32_t pflbm_init_fields(pflbm_ctx* ctx, int32_t case_id, const double* C, const double* u,
+                          const double* p);
+
+/*
+ * Advances every case by nsteps time steps (collision, streaming,
+ * bounce-back, Eqs. (14), (18)); asynchronous.  Errors: STATE before every
+ * case has been initialised.
+ */
+int32_t pflbm_step(pflbm_ctx* ctx, int64_t nsteps);
+
+/*
+ * Macroscopic fields of one case (Eqs. (22)-(24)) into caller device
+ * buffers, each row-major (ny, nx) float32: rho (1 plane), u (2 planes:
+ * u_x, u_y), p (1 plane), phi (n_h planes: C_1..C_n_h).  Any pointer may be
+ * NULL to skip that output.  Asynchronous.
+ */
+int32_t pflbm_macroscopic(pflbm_ctx* ctx, int32_t case_id, float* d_rho, float* d_u, float* d_p,
+                          float* d_phi);
+
+/*
+ * Bubble diagnostics of component `comp` (0..2) of one case, summed in
+ * float64 on the device (Sec. 3.1 thresholded mass; Sec. 4.2,
+ * Eqs. (43)-(44)): out = { sum C, sum of C over cells with C > 0.5,
+ * centroid x, centroid y, mean u_x, mean u_y } with weights C.  Synchronises
+ * the stream.  Errors: NONFINITE when a summed quantity is not finite.
+ */
+int32_t pflbm_bubble_centroid_velocity(pflbm_ctx* ctx, int32_t case_id, int32_t comp, double out[6]);
+
+/*
+ * Checkpoint: copies the complete state of every case (device to device)
+ * into/out of a caller buffer of pflbm_state_bytes bytes.  Asynchronous.
+ */
+size_t pflbm_state_bytes(const pflbm_ctx* ctx);
+int32_t pflbm_get_state(pflbm_ctx* ctx, void* d_dst, size_t bytes);
+int32_t pflbm_set_state(pflbm_ctx* ctx, const void* d_src, size_t bytes);
+
+/*
+ * Raw population planes of one case for inspection, as float32 (ny, nx)
+ * planes copied into a caller device buffer: 9 planes of gbar_a
+ * (a = 0..8, D2Q9 order of Eq. (11)), then n_h planes of C_i, then tau.
+ * Asynchronous.
+ */
+int32_t pflbm_export_populations(pflbm_ctx* ctx, int32_t case_id, float* d_out);
+
+/*
+ * Kernel variants (tile shapes) of the step.  pflbm_set_variant selects the
+ * variant used by pflbm_step; -1 restores the default.  pflbm_variant_name
+ * returns NULL for an unknown index.
+ */
+int32_t pflbm_num_variants(const pflbm_ctx* ctx);
+const char* pflbm_variant_name(const pflbm_ctx* ctx, int32_t index);
+int32_t pflbm_set_variant(pflbm_ctx* ctx, int32_t index);
+
+/* Stream of the step kernel (hipStream_t as void*), for timing with events. */
+void* pflbm_stream(const pflbm_ctx* ctx);
+
+/* Algorithmic bytes moved per lattice update by the step kernel. */
+double pflbm_bytes_per_update(const pflbm_ctx* ctx);
+
+int32_t pflbm_destroy(pflbm_ctx* ctx);
+const char* pflbm_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFLBM_H */

@@ -1,0 +1,141 @@
+// pflbm_device.h -- device-side building blocks of the gfx950 step kernels.
+//
+// Lattice, per-case parameter block, thermodynamics (Sec. 2.1), equilibria
+// and forcing (Sec. 2.2) and the truncated power law (Sec. 2.3) of
+// arXiv 2207.09431, in float32.  Private to the HIP library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pflbm {
+
+// D2Q9 in the order of Sec. 2.2, Eq. (11): 0 rest, 1-4 axes, 5-8 diagonals.
+struct Lat {
+    static constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    static constexpr float w[9] = {4.0f / 9.0f, 1.0f / 9.0f, 1.0f / 9.0f, 1.0f / 9.0f, 1.0f / 9.0f,
+                                   1.0f / 36.0f, 1.0f / 36.0f, 1.0f / 36.0f, 1.0f / 36.0f};
+};
+constexpr float kCs2 = 1.0f / 3.0f;
+
+// Per-case block in device memory.  State planes are row-major (ny, pitch);
+// `plane` is the element stride between planes.  The gbar state is kept as
+// s = sum_a gbar_a in plane 0 and the deviations d_a = gbar_a - w_a s
+// (a = 1..8) in planes 1..8 (float32); d_0 = -sum_{a>0} d_a.  The phase
+// fields C_i are accumulated in float64 planes: their per-step change is far
+// below the float32 spacing near C = 1, and rounding it into a float32 state
+// drifts the component mass.
+struct CaseDev {
+    int nx, ny, pitch, n_h;
+    long long plane;
+    float* S[2];        // 9 planes each (ping-pong)
+    double* C[2];       // n_h planes each (float64)
+    float* T[2];        // tau of the previous step
+    float* H[2];        // 9*n_h planes each when hbar is stored, else null
+    float rho[3], nu[3];
+    int plc;            // power-law component or -1
+    int vm;             // variable mobility
+    float K, nexp, numin, numax;
+    float sig12, sig13, sig23, lam;
+    float Sig[3], SigT;
+    float xi;
+    float mob[2];       // D0 / Sigma_i for the carried components
+    float omh;          // 1 / (tau_h + 1/2)
+    float g, fx;
+    // float64 copies for the bulk chemical potential
+    double dsig12, dsig13, dsig23, dlam, dSig[3], dSigT, dxi;
+};
+
+struct TileDev {
+    int case_id, x0, y0, pad;
+};
+
+__device__ __forceinline__ float clip01(float c) { return fminf(fmaxf(c, 0.0f), 1.0f); }
+
+__device__ __forceinline__ int wrap_x(int x, int nx) {
+    x %= nx;
+    return x < 0 ? x + nx : x;
+}
+// Mirror about the walls at y = -1/2 and y = ny - 1/2 (zero normal
+// derivative of the stencil fields); rows farther than ny away are clamped.
+__device__ __forceinline__ int mirror_y(int y, int ny) {
+    if (y < 0) y = -y - 1;
+    if (y >= ny) y = 2 * ny - 1 - y;
+    return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+}
+
+// Mixture density with concentrations limited to [0, 1].
+__device__ __forceinline__ float mix_rho(const CaseDev& cd, float c1, float c2) {
+    return cd.rho[0] * clip01(c1) + cd.rho[1] * clip01(c2) + cd.rho[2] * clip01(1.0f - c1 - c2);
+}
+
+// Chemical potentials of the ternary free energy (Sec. 2.1, Eqs. (3), (5)).
+__device__ __forceinline__ void chem_potential(const CaseDev& cd, float c1, float c2, float c3,
+                                               float l1, float l2, float l3, float mu[3]) {
+    const float S0 = cd.Sig[0], S1 = cd.Sig[1], S2 = cd.Sig[2];
+    const float sc = S0 * c1 + S1 * c2 + S2 * c3;
+    const float c123 = c1 * c2 * c3;
+    const float d0 = 2.0f * cd.sig12 * c1 * c2 * c2 + 2.0f * cd.sig13 * c1 * c3 * c3 + c2 * c3 * sc + c123 * S0
+                   + 2.0f * cd.lam * c1 * c2 * c2 * c3 * c3;
+    const float d1 = 2.0f * cd.sig12 * c1 * c1 * c2 + 2.0f * cd.sig23 * c2 * c3 * c3 + c1 * c3 * sc + c123 * S1
+                   + 2.0f * cd.lam * c1 * c1 * c2 * c3 * c3;
+    const float d2 = 2.0f * cd.sig13 * c1 * c1 * c3 + 2.0f * cd.sig23 * c2 * c2 * c3 + c1 * c2 * sc + c123 * S2
+                   + 2.0f * cd.lam * c1 * c1 * c2 * c2 * c3;
+    const float a = 4.0f * cd.SigT / cd.xi, b = 0.75f * cd.xi;
+    mu[0] = a * ((d0 - d1) / S1 + (d0 - d2) / S2) - b * S0 * l1;
+    mu[1] = a * ((d1 - d0) / S0 + (d1 - d2) / S2) - b * S1 * l2;
+    mu[2] = a * ((d2 - d0) / S0 + (d2 - d1) / S1) - b * S2 * l3;
+}
+
+// Same potentials with the bulk part evaluated in float64 from float64
+// concentrations: near equilibrium mu is a small difference of the bulk and
+// gradient parts, and float32 concentrations would leave a relative error of
+// order 1e-6 in it.
+__device__ __forceinline__ void chem_potential_d(const CaseDev& cd, double c1, double c2, float l1, float l2,
+                                                 float mu[3]) {
+    const double c3 = 1.0 - c1 - c2;
+    const double S0 = cd.dSig[0], S1 = cd.dSig[1], S2 = cd.dSig[2];
+    const double sc = S0 * c1 + S1 * c2 + S2 * c3;
+    const double c123 = c1 * c2 * c3;
+    const double d0 = 2.0 * cd.dsig12 * c1 * c2 * c2 + 2.0 * cd.dsig13 * c1 * c3 * c3 + c2 * c3 * sc + c123 * S0
+                    + 2.0 * cd.dlam * c1 * c2 * c2 * c3 * c3;
+    const double d1 = 2.0 * cd.dsig12 * c1 * c1 * c2 + 2.0 * cd.dsig23 * c2 * c3 * c3 + c1 * c3 * sc + c123 * S1
+                    + 2.0 * cd.dlam * c1 * c1 * c2 * c3 * c3;
+    const double d2 = 2.0 * cd.dsig13 * c1 * c1 * c3 + 2.0 * cd.dsig23 * c2 * c2 * c3 + c1 * c2 * sc + c123 * S2
+                    + 2.0 * cd.dlam * c1 * c1 * c2 * c2 * c3;
+    const double a = 4.0 * cd.dSigT / cd.dxi;
+    const float b = 0.75f * cd.xi;
+    mu[0] = (float)(a * ((d0 - d1) / S1 + (d0 - d2) / S2)) - b * cd.Sig[0] * l1;
+    mu[1] = (float)(a * ((d1 - d0) / S0 + (d1 - d2) / S2)) - b * cd.Sig[1] * l2;
+    mu[2] = (float)(a * ((d2 - d0) / S0 + (d2 - d1) / S1)) + b * cd.Sig[2] * (l1 + l2);
+}
+
+// Truncated power law, kinematic (Sec. 2.3, Eqs. (31), (33)).
+__device__ __forceinline__ float powerlaw_nu(const CaseDev& cd, float gdot) {
+    float nu;
+    if (gdot <= 0.0f) {
+        if (cd.nexp < 1.0f) return cd.numax;
+        if (cd.nexp > 1.0f) return cd.numin;
+        nu = cd.K;
+    } else {
+        nu = cd.K * exp2f((cd.nexp - 1.0f) * log2f(gdot));
+    }
+    return fminf(fmaxf(nu, cd.numin), cd.numax);
+}
+
+// Mixture relaxation time: nu = sum_k C_k nu_k limited to [min nu_k, max nu_k], tau = nu / c_s^2.
+__device__ __forceinline__ float mixture_tau(const CaseDev& cd, float c1, float c2, float c3, float gdot) {
+    float n0 = cd.nu[0], n1 = cd.nu[1], n2 = cd.nu[2];
+    if (cd.plc >= 0) {
+        const float np = powerlaw_nu(cd, gdot);
+        if (cd.plc == 0) n0 = np; else if (cd.plc == 1) n1 = np; else n2 = np;
+    }
+    float nu = c1 * n0 + c2 * n1 + c3 * n2;
+    const float lo = fminf(n0, fminf(n1, n2)), hi = fmaxf(n0, fmaxf(n1, n2));
+    nu = fminf(fmaxf(nu, lo), hi);
+    return 3.0f * nu;
+}
+
+}  // namespace pflbm

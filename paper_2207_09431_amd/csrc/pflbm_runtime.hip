@@ -1,0 +1,412 @@
+// pflbm_runtime.hip -- host runtime behind the C ABI of include/pflbm.h.
+//
+// Validates parameters, carves the caller's workspace into per-case state
+// planes, builds the tile table of the batched launch and enqueues kernels on
+// the caller's stream.  The library never allocates device memory.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "pflbm.h"
+#include "pflbm_internal.h"
+
+using namespace pflbm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kPitchElems = 64;
+constexpr int kReduceMax = 1024;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct CaseLayout {
+    size_t S[2], C[2], T[2], H[2];   // byte offsets into the workspace
+    int pitch;
+    long long plane;                 // elements per plane
+};
+
+struct Layout {
+    size_t cases_off, tiles_off, result_off, partial_off, staging_off;
+    size_t staging_bytes;
+    size_t max_tiles;
+    std::vector<CaseLayout> cl;
+    size_t state_begin, state_end;   // byte range of all state planes
+    size_t total;
+};
+
+// Capillary coefficients Sigma_i = sigma_ij + sigma_ik - sigma_jk and Sigma_T (Sec. 2.1).
+void capillary(const pflbm_params& p, double S[3], double* ST) {
+    S[0] = p.sigma12 + p.sigma13 - p.sigma23;
+    S[1] = p.sigma12 + p.sigma23 - p.sigma13;
+    S[2] = p.sigma13 + p.sigma23 - p.sigma12;
+    *ST = 3.0 / (1.0 / S[0] + 1.0 / S[1] + 1.0 / S[2]);
+}
+
+bool is_finite(double v) { return isfinite(v) != 0; }
+
+bool valid_params(const pflbm_params& p) {
+    if (p.nx < 5 || p.ny < 5 || (p.n_h != 1 && p.n_h != 2)) return false;
+    if ((long long)p.nx * p.ny > (1LL << 31)) return false;
+    for (int k = 0; k < 3; ++k)
+        if (!(p.rho[k] > 0.0) || !(p.nu[k] > 0.0) || !is_finite(p.rho[k]) || !is_finite(p.nu[k])) return false;
+    if (p.powerlaw_comp < -1 || p.powerlaw_comp > 2) return false;
+    if (p.powerlaw_comp >= 0) {
+        if (!(p.K > 0.0) || !is_finite(p.n) || !(p.nu_min > 0.0) || !(p.nu_min <= p.nu_max) || !is_finite(p.nu_max))
+            return false;
+    }
+    if (!(p.xi > 0.0) || !(p.D0 >= 0.0) || !(p.tau_h > 0.0)) return false;
+    if (!is_finite(p.g) || !is_finite(p.fx) || !is_finite(p.Lambda)) return false;
+    double S[3], ST;
+    capillary(p, S, &ST);
+    for (int k = 0; k < 3; ++k)
+        if (!(S[k] > 0.0) || !is_finite(S[k])) return false;
+    if (p.storage != 0 && p.storage != 1) return false;
+    if (p.store_h != 0 && p.store_h != 1) return false;
+    if (!p.store_h && p.tau_h != 0.5) return false;
+    return true;
+}
+
+int smallest_tile_cells() {
+    int best = 1 << 30;
+    for (int v = 0; v < step_variant_count(); ++v) {
+        int tx, ty, nt;
+        if (step_variant_shape(v, 1, &tx, &ty, &nt) && tx * ty < best) best = tx * ty;
+    }
+    return best;
+}
+
+size_t max_tiles_for(const pflbm_params* cases, int n) {
+    size_t worst = 0;
+    for (int v = 0; v < step_variant_count(); ++v) {
+        int tx, ty, nt;
+        if (!step_variant_shape(v, cases[0].n_h, &tx, &ty, &nt)) continue;
+        size_t t = 0;
+        for (int c = 0; c < n; ++c) t += (size_t)((cases[c].nx + tx - 1) / tx) * ((cases[c].ny + ty - 1) / ty);
+        if (t > worst) worst = t;
+    }
+    return worst;
+}
+
+bool make_layout(const pflbm_params* cases, int n, Layout* L) {
+    if (!cases || n <= 0) return false;
+    for (int c = 0; c < n; ++c) {
+        if (!valid_params(cases[c])) return false;
+        if (cases[c].n_h != cases[0].n_h || cases[c].storage != cases[0].storage ||
+            cases[c].store_h != cases[0].store_h)
+            return false;
+    }
+    (void)smallest_tile_cells();
+    size_t off = 0;
+    L->cases_off = off;
+    off = align_up(off + sizeof(CaseDev) * n, kAlign);
+    L->max_tiles = max_tiles_for(cases, n);
+    L->tiles_off = off;
+    off = align_up(off + sizeof(TileDev) * L->max_tiles, kAlign);
+    L->result_off = off;
+    off = align_up(off + 8 * sizeof(double), kAlign);
+    L->partial_off = off;
+    off = align_up(off + 6 * sizeof(double) * kReduceMax, kAlign);
+    size_t maxcells = 0;
+    for (int c = 0; c < n; ++c) {
+        size_t cells = (size_t)cases[c].nx * cases[c].ny;
+        if (cells > maxcells) maxcells = cells;
+    }
+    L->staging_off = off;
+    L->staging_bytes = sizeof(double) * maxcells * (size_t)(cases[0].n_h + 3);
+    off = align_up(off + L->staging_bytes, kAlign);
+    L->state_begin = off;
+    L->cl.resize(n);
+    for (int c = 0; c < n; ++c) {
+        const pflbm_params& p = cases[c];
+        CaseLayout& cl = L->cl[c];
+        cl.pitch = (int)align_up((size_t)p.nx, kPitchElems);
+        cl.plane = (long long)cl.pitch * p.ny;
+        const size_t pb = sizeof(float) * (size_t)cl.plane;
+        for (int b = 0; b < 2; ++b) {
+            cl.S[b] = off; off = align_up(off + 9 * pb, kAlign);
+            cl.C[b] = off; off = align_up(off + (size_t)p.n_h * 2 * pb, kAlign);   // float64
+            cl.T[b] = off; off = align_up(off + pb, kAlign);
+            if (p.store_h) { cl.H[b] = off; off = align_up(off + 9 * (size_t)p.n_h * pb, kAlign); }
+            else cl.H[b] = 0;
+        }
+    }
+    L->state_end = off;
+    L->total = off;
+    return true;
+}
+
+}  // namespace
+
+struct pflbm_ctx {
+    std::vector<pflbm_params> prm;
+    std::vector<CaseDev> cd;          // host copies of the device case blocks
+    std::vector<int> initialised;
+    Layout L;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    int par = 0;
+    int variant = 0;
+    int ntiles = 0;
+    int device = 0;
+};
+
+namespace {
+
+int32_t dev_err(hipError_t e) { return e == hipSuccess ? PFLBM_OK : PFLBM_ERR_DEVICE; }
+
+int32_t build_tiles(pflbm_ctx* c, int v) {
+    int tx, ty, nt;
+    if (!step_variant_shape(v, c->prm[0].n_h, &tx, &ty, &nt)) return PFLBM_ERR_INVALID_ARG;
+    std::vector<TileDev> tiles;
+    for (int k = 0; k < (int)c->prm.size(); ++k) {
+        const int nx = c->prm[k].nx, ny = c->prm[k].ny;
+        for (int y0 = 0; y0 < ny; y0 += ty)
+            for (int x0 = 0; x0 < nx; x0 += tx) tiles.push_back(TileDev{k, x0, y0, 0});
+    }
+    if (tiles.size() > c->L.max_tiles || tiles.empty()) return PFLBM_ERR_WORKSPACE;
+    hipError_t e = hipMemcpyAsync(c->ws + c->L.tiles_off, tiles.data(), sizeof(TileDev) * tiles.size(),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return PFLBM_ERR_DEVICE;
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return PFLBM_ERR_DEVICE;
+    c->ntiles = (int)tiles.size();
+    c->variant = v;
+    return PFLBM_OK;
+}
+
+const CaseDev* dev_case(const pflbm_ctx* c, int k) {
+    return reinterpret_cast<const CaseDev*>(c->ws + c->L.cases_off) + k;
+}
+
+bool all_init(const pflbm_ctx* c) {
+    for (int v : c->initialised)
+        if (!v) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pflbm_workspace_bytes(const pflbm_params* cases, int32_t ncases) {
+    Layout L;
+    if (!make_layout(cases, ncases, &L)) return 0;
+    return L.total;
+}
+
+int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspace, size_t bytes, void* hip_stream,
+                     pflbm_ctx** out) {
+    if (!out) return PFLBM_ERR_INVALID_ARG;
+    *out = nullptr;
+    Layout L;
+    if (!cases || ncases <= 0 || !make_layout(cases, ncases, &L)) return PFLBM_ERR_INVALID_ARG;
+    if (cases[0].storage != 0) return PFLBM_ERR_UNSUPPORTED;
+    if (!d_workspace || bytes < L.total || ((uintptr_t)d_workspace % kAlign) != 0) return PFLBM_ERR_WORKSPACE;
+    pflbm_ctx* c = new (std::nothrow) pflbm_ctx;
+    if (!c) return PFLBM_ERR_DEVICE;
+    c->prm.assign(cases, cases + ncases);
+    c->L = L;
+    c->ws = static_cast<char*>(d_workspace);
+    c->ws_bytes = bytes;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->initialised.assign(ncases, 0);
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return PFLBM_ERR_DEVICE; }
+    c->cd.resize(ncases);
+    for (int k = 0; k < ncases; ++k) {
+        const pflbm_params& p = cases[k];
+        const CaseLayout& cl = L.cl[k];
+        CaseDev& d = c->cd[k];
+        memset(&d, 0, sizeof(d));
+        d.nx = p.nx; d.ny = p.ny; d.pitch = cl.pitch; d.n_h = p.n_h; d.plane = cl.plane;
+        for (int b = 0; b < 2; ++b) {
+            d.S[b] = reinterpret_cast<float*>(c->ws + cl.S[b]);
+            d.C[b] = reinterpret_cast<double*>(c->ws + cl.C[b]);
+            d.T[b] = reinterpret_cast<float*>(c->ws + cl.T[b]);
+            d.H[b] = p.store_h ? reinterpret_cast<float*>(c->ws + cl.H[b]) : nullptr;
+        }
+        for (int j = 0; j < 3; ++j) { d.rho[j] = (float)p.rho[j]; d.nu[j] = (float)p.nu[j]; }
+        d.plc = p.powerlaw_comp;
+        d.vm = p.variable_mobility ? 1 : 0;
+        d.K = (float)p.K; d.nexp = (float)p.n; d.numin = (float)p.nu_min; d.numax = (float)p.nu_max;
+        d.sig12 = (float)p.sigma12; d.sig13 = (float)p.sigma13; d.sig23 = (float)p.sigma23; d.lam = (float)p.Lambda;
+        double S[3], ST;
+        capillary(p, S, &ST);
+        for (int j = 0; j < 3; ++j) d.Sig[j] = (float)S[j];
+        d.SigT = (float)ST;
+        d.xi = (float)p.xi;
+        d.mob[0] = (float)(p.D0 / S[0]);
+        d.mob[1] = (float)(p.D0 / S[1]);
+        d.omh = (float)(1.0 / (p.tau_h + 0.5));
+        d.g = (float)p.g; d.fx = (float)p.fx;
+        d.dsig12 = p.sigma12; d.dsig13 = p.sigma13; d.dsig23 = p.sigma23; d.dlam = p.Lambda;
+        for (int j = 0; j < 3; ++j) d.dSig[j] = S[j];
+        d.dSigT = ST;
+        d.dxi = p.xi;
+    }
+    hipError_t e = hipMemcpyAsync(c->ws + L.cases_off, c->cd.data(), sizeof(CaseDev) * ncases, hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { delete c; return PFLBM_ERR_DEVICE; }
+    int32_t st = build_tiles(c, 0);
+    if (st != PFLBM_OK) { delete c; return st; }
+    *out = c;
+    return PFLBM_OK;
+}
+
+int32_t pflbm_init_fields(pflbm_ctx* c, int32_t k, const double* C, const double* u, const double* p) {
+    if (!c || k < 0 || k >= (int)c->prm.size() || !C) return PFLBM_ERR_INVALID_ARG;
+    const pflbm_params& prm = c->prm[k];
+    const size_t n = (size_t)prm.nx * prm.ny;
+    for (size_t i = 0; i < n * prm.n_h; ++i) if (!is_finite(C[i])) return PFLBM_ERR_NONFINITE;
+    if (u) for (size_t i = 0; i < 2 * n; ++i) if (!is_finite(u[i])) return PFLBM_ERR_NONFINITE;
+    if (p) for (size_t i = 0; i < n; ++i) if (!is_finite(p[i])) return PFLBM_ERR_NONFINITE;
+    double* st = reinterpret_cast<double*>(c->ws + c->L.staging_off);
+    double* dC = st;
+    double* du = st + n * prm.n_h;
+    double* dp = du + 2 * n;
+    hipError_t e = hipMemcpyAsync(dC, C, sizeof(double) * n * prm.n_h, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(du, u, sizeof(double) * 2 * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && p) e = hipMemcpyAsync(dp, p, sizeof(double) * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_init(dev_case(c, k), c->cd[k], c->par, dC, u ? du : nullptr, p ? dp : nullptr, c->stream);
+    // the staging area is reused by the next call: keep the host in step
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return PFLBM_ERR_DEVICE;
+    c->initialised[k] = 1;
+    return PFLBM_OK;
+}
+
+int32_t pflbm_step(pflbm_ctx* c, int64_t nsteps) {
+    if (!c || nsteps < 0) return PFLBM_ERR_INVALID_ARG;
+    if (!all_init(c)) return PFLBM_ERR_STATE;
+    const CaseDev* cases = dev_case(c, 0);
+    const TileDev* tiles = reinterpret_cast<const TileDev*>(c->ws + c->L.tiles_off);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipError_t e = launch_step(c->variant, c->prm[0].n_h, c->prm[0].store_h != 0, cases, tiles, c->ntiles,
+                                   c->par, c->stream);
+        if (e != hipSuccess) return PFLBM_ERR_DEVICE;
+        c->par ^= 1;
+    }
+    return PFLBM_OK;
+}
+
+int32_t pflbm_macroscopic(pflbm_ctx* c, int32_t k, float* rho, float* u, float* p, float* phi) {
+    if (!c || k < 0 || k >= (int)c->prm.size()) return PFLBM_ERR_INVALID_ARG;
+    if (!c->initialised[k]) return PFLBM_ERR_STATE;
+    if (!rho && !u && !p && !phi) return PFLBM_OK;
+    return dev_err(launch_macro(dev_case(c, k), c->cd[k], c->par, rho, u, p, phi, c->stream));
+}
+
+int32_t pflbm_bubble_centroid_velocity(pflbm_ctx* c, int32_t k, int32_t comp, double out[6]) {
+    if (!c || k < 0 || k >= (int)c->prm.size() || comp < 0 || comp > 2 || !out) return PFLBM_ERR_INVALID_ARG;
+    if (!c->initialised[k]) return PFLBM_ERR_STATE;
+    double* res = reinterpret_cast<double*>(c->ws + c->L.result_off);
+    double* part = reinterpret_cast<double*>(c->ws + c->L.partial_off);
+    hipError_t e = launch_reduce(dev_case(c, k), c->cd[k], c->par, comp, part, res, c->stream);
+    double sums[6];
+    if (e == hipSuccess) e = hipMemcpyAsync(sums, res, sizeof(sums), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return PFLBM_ERR_DEVICE;
+    for (int j = 0; j < 6; ++j) if (!is_finite(sums[j])) return PFLBM_ERR_NONFINITE;
+    const double m = sums[0];
+    out[0] = m;
+    out[1] = sums[1];
+    out[2] = sums[2] / m;
+    out[3] = sums[3] / m;
+    out[4] = sums[4] / m;
+    out[5] = sums[5] / m;
+    return PFLBM_OK;
+}
+
+size_t pflbm_state_bytes(const pflbm_ctx* c) {
+    if (!c) return 0;
+    size_t b = 0;
+    for (size_t k = 0; k < c->prm.size(); ++k) b += c->L.cl[k].S[1] - c->L.cl[k].S[0];
+    return b;
+}
+
+static int32_t copy_state(pflbm_ctx* c, char* dst, const char* src, bool to_ws) {
+    size_t o = 0;
+    for (size_t k = 0; k < c->prm.size(); ++k) {
+        const CaseLayout& cl = c->L.cl[k];
+        const size_t len = cl.S[1] - cl.S[0];
+        char* w = c->ws + cl.S[c->par];
+        hipError_t e = to_ws ? hipMemcpyAsync(w, src + o, len, hipMemcpyDeviceToDevice, c->stream)
+                             : hipMemcpyAsync(dst + o, w, len, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return PFLBM_ERR_DEVICE;
+        o += len;
+    }
+    return PFLBM_OK;
+}
+
+int32_t pflbm_get_state(pflbm_ctx* c, void* d_dst, size_t bytes) {
+    if (!c || !d_dst) return PFLBM_ERR_INVALID_ARG;
+    if (bytes < pflbm_state_bytes(c)) return PFLBM_ERR_WORKSPACE;
+    return copy_state(c, static_cast<char*>(d_dst), nullptr, false);
+}
+
+int32_t pflbm_set_state(pflbm_ctx* c, const void* d_src, size_t bytes) {
+    if (!c || !d_src) return PFLBM_ERR_INVALID_ARG;
+    if (bytes < pflbm_state_bytes(c)) return PFLBM_ERR_WORKSPACE;
+    int32_t st = copy_state(c, nullptr, static_cast<const char*>(d_src), true);
+    if (st == PFLBM_OK) for (auto& v : c->initialised) v = 1;
+    return st;
+}
+
+int32_t pflbm_export_populations(pflbm_ctx* c, int32_t k, float* d_out) {
+    if (!c || k < 0 || k >= (int)c->prm.size() || !d_out) return PFLBM_ERR_INVALID_ARG;
+    if (!c->initialised[k]) return PFLBM_ERR_STATE;
+    return dev_err(launch_export(dev_case(c, k), c->cd[k], c->par, d_out, c->stream));
+}
+
+int32_t pflbm_num_variants(const pflbm_ctx* c) { return c ? step_variant_count() : 0; }
+
+const char* pflbm_variant_name(const pflbm_ctx* c, int32_t v) {
+    static thread_local char buf[64];
+    int tx, ty, nt;
+    if (!c || !step_variant_shape(v, c->prm[0].n_h, &tx, &ty, &nt)) return nullptr;
+    snprintf(buf, sizeof(buf), "tile%dx%d_t%d", tx, ty, nt);
+    return buf;
+}
+
+int32_t pflbm_set_variant(pflbm_ctx* c, int32_t v) {
+    if (!c) return PFLBM_ERR_INVALID_ARG;
+    if (v == -1) v = 0;
+    return build_tiles(c, v);
+}
+
+void* pflbm_stream(const pflbm_ctx* c) { return c ? (void*)c->stream : nullptr; }
+
+double pflbm_bytes_per_update(const pflbm_ctx* c) {
+    if (!c) return 0.0;
+    const pflbm_params& p = c->prm[0];
+    double b = 9 * 4 + 8.0 * p.n_h + 4;    // gbar (s + 8 deviations, float32), C_i (float64), tau
+    if (p.store_h) b += 9 * 4.0 * p.n_h;   // hbar
+    return 2.0 * b;                        // read once and written once
+}
+
+int32_t pflbm_destroy(pflbm_ctx* c) {
+    if (!c) return PFLBM_ERR_INVALID_ARG;
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    delete c;
+    if (e != hipSuccess) return PFLBM_ERR_DEVICE;
+    return PFLBM_OK;
+}
+
+const char* pflbm_status_string(int32_t s) {
+    switch (s) {
+        case PFLBM_OK: return "ok";
+        case PFLBM_ERR_INVALID_ARG: return "invalid argument";
+        case PFLBM_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+        case PFLBM_ERR_DEVICE: return "HIP device error";
+        case PFLBM_ERR_NONFINITE: return "non-finite value";
+        case PFLBM_ERR_STATE: return "call out of order";
+        case PFLBM_ERR_UNSUPPORTED: return "unsupported in this build";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -93,21 +93,24 @@ def _case(params, C, u=None, p=None, name=""):
 
 
 def hydrostatic_pressure(C, params: dict) -> np.ndarray:
-    """Initial pressure in hydrostatic balance with F_b = -rho g j along each
-    column: p(y) - p(y+1) = g (rho(y) + rho(y+1)) / 2 from the top row down,
-    shifted to zero mean.  rho = sum_k rho_k C_k with each C_k limited to
-    [0, 1].  Starting from p = 0 instead launches a pressure transient that a
-    density ratio of 1000 does not survive."""
+    """Initial pressure of the liquid at rest under F_b = -rho g j:
+    p(y) = rho_l g (y_c - y) with y_c the mid-height, the same in every column.
+    Starting from p = 0 instead launches a pressure transient that a density
+    ratio of 1000 does not survive for the larger g.  (Integrating the mixture
+    density along each column is worse: columns that cross a bubble get a
+    lower pressure below it, and the resulting horizontal pressure jump
+    accelerates the gas of any bubble beneath.)"""
     C = np.asarray(C, dtype=np.float64)
-    c1 = C[0]
-    c2 = C[1] if C.shape[0] > 1 else np.zeros_like(c1)
-    r = params["rho"]
-    rho = (r[0] * np.clip(c1, 0, 1) + r[1] * np.clip(c2, 0, 1) + r[2] * np.clip(1 - c1 - c2, 0, 1))
-    g = float(params["g"])
-    p = np.zeros_like(rho)
-    for y in range(rho.shape[0] - 2, -1, -1):
-        p[y] = p[y + 1] + g * 0.5 * (rho[y] + rho[y + 1])
-    return p - p.mean()
+    ny, nx = C.shape[-2:]
+    rho_l = float(params["rho"][2])
+    y = np.arange(ny, dtype=np.float64)[:, None] * np.ones((1, nx))
+    return rho_l * float(params["g"]) * (0.5 * (ny - 1) - y)
+
+
+# The density-ratio-1000 workloads below start from p = 0 (the liquid then
+# settles into hydrostatic balance through a weak acoustic transient): a
+# hydrostatic start pushes the gas of bubbles with R >= 40 into a divergence
+# within 60 steps, while p = 0 stays quiet (checked with the oracle).
 
 
 def gravity_for_gas_mach(radius: float, density_ratio: float, mach: float = 0.01) -> float:
@@ -161,7 +164,7 @@ def powerlaw_bubble(n: float = 0.5, eo: float = 10.0, nx: int = 200, ny: int = 4
                K=K, n=n, nu_min=1e-4, nu_max=1.0, variable_mobility=0,
                sigma12=sigma, sigma13=sigma, sigma23=sigma, g=g)
     C = bubble_field(nx, ny, [(nx / 2.0, 0.6 * nx, d / 2.0)], prm["xi"])[None]
-    return _case(prm, C, None, hydrostatic_pressure(C, prm), f"powerlaw_bubble_{nx}x{ny}_n{n:.3f}_Eo{eo:.2f}")
+    return _case(prm, C, None, None, f"powerlaw_bubble_{nx}x{ny}_n{n:.3f}_Eo{eo:.2f}")
 
 
 def three_component(variable_mobility: int = 0, nx: int = 256, ny: int = 512) -> dict:
@@ -178,7 +181,7 @@ def three_component(variable_mobility: int = 0, nx: int = 256, ny: int = 512) ->
     c1 = bubble_field(nx, ny, [(128.0 * sx, 160.0 * sy, 40.0 * s)], prm["xi"])
     c2 = bubble_field(nx, ny, [(128.0 * sx, 330.0 * sy, 25.0 * s)], prm["xi"])
     C = np.stack([c1, c2])
-    return _case(prm, C, None, hydrostatic_pressure(C, prm), f"three_component_{nx}x{ny}")
+    return _case(prm, C, None, None, f"three_component_{nx}x{ny}")
 
 
 def place_bubbles(nx: int, ny: int, count: int, rmin: float, rmax: float, xi: float, seed: int,
@@ -221,15 +224,13 @@ def large_domain_params(nx: int = 2048, ny: int = 4096, storage: int = 0) -> dic
     return prm
 
 
-def many_bubbles(nx: int = 2048, ny: int = 4096, count: int = 64, seed: int = 5, storage: int = 0,
-                 with_pressure: bool = True) -> dict:
+def many_bubbles(nx: int = 2048, ny: int = 4096, count: int = 64, seed: int = 5, storage: int = 0) -> dict:
     """Large single domain with `count` non-overlapping seeded bubbles,
     R ~ U[25, 40], in the power-law liquid of `large_domain_params`."""
     prm = large_domain_params(nx, ny, storage)
     bubbles = place_bubbles(nx, ny, count, LARGE_RMIN, LARGE_RMAX, prm["xi"], seed)
     C = bubble_field(nx, ny, bubbles, prm["xi"])[None]
-    p = hydrostatic_pressure(C, prm) if with_pressure else None
-    case = _case(prm, C, None, p, f"many_bubbles_{nx}x{ny}_{count}")
+    case = _case(prm, C, None, None, f"many_bubbles_{nx}x{ny}_{count}")
     case["bubbles"] = bubbles
     return case
 
@@ -248,7 +249,7 @@ def many_bubbles_crop(nx: int = 2048, ny: int = 4096, count: int = 64, seed: int
               if x - r - prm["xi"] >= x0 and x + r + prm["xi"] < x0 + cw
               and y - r - prm["xi"] >= y0 and y + r + prm["xi"] < y0 + ch]
     C = bubble_field(cw, ch, inside, prm["xi"])[None]
-    case = _case(prm, C, None, hydrostatic_pressure(C, prm), f"many_bubbles_crop_{cw}x{ch}")
+    case = _case(prm, C, None, None, f"many_bubbles_crop_{cw}x{ch}")
     case["bubbles"] = inside
     case["origin"] = (x0, y0)
     return case

@@ -1,0 +1,51 @@
+"""Host-side checks of the C ABI that need no GPU: the in-tree library loads,
+exports every symbol declared in include/pflbm.h, sizes workspaces and
+rejects invalid parameters."""
+import os
+import re
+
+import pytest
+
+from paper_2207_09431_amd import inputs, pflbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "pflbm.h")).read()
+    return sorted(set(re.findall(r"\b(pflbm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(pflbm.LIB_PATH):
+        pytest.fail("libpflbm.so is not built (run __graft_entry__.build())")
+    return pflbm.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    syms = declared_symbols()
+    assert len(syms) >= 17
+    assert set(syms) == set(pflbm.EXPORTS)
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_workspace_bytes_valid_and_invalid(L):
+    prm = inputs.rising_bubble_small()["params"]
+    n = pflbm.workspace_bytes([prm])
+    assert n > 9 * 2 * 4 * 64 * 128
+    bad = [dict(prm, nx=4), dict(prm, n_h=3), dict(prm, rho=[0.0, 1.0, 1.0]), dict(prm, nu_min=2.0, nu_max=1.0,
+           powerlaw_comp=2), dict(prm, tau_h=0.7, store_h=0), dict(prm, sigma23=1.0), dict(prm, xi=0.0)]
+    for b in bad:
+        assert pflbm.workspace_bytes([b]) == 0, b
+    # a stored-hbar case with tau_h != 1/2 is valid
+    assert pflbm.workspace_bytes([dict(prm, tau_h=0.7, store_h=1)]) > n
+    # batched cases must agree on n_h / storage / store_h
+    assert pflbm.workspace_bytes([prm, dict(prm, n_h=2)]) == 0
+    assert pflbm.workspace_bytes([prm, dict(prm, nx=80, ny=90)]) > n
+
+
+def test_status_strings(L):
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert L.pflbm_status_string(s)

@@ -1,0 +1,197 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  FP32 tolerance: relative L2 of u and C <= 1e-5 after the
+stated number of steps."""
+import numpy as np
+import pytest
+
+from oracle.pfo import Oracle, run_case
+from paper_2207_09431_amd import inputs
+from helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return t
+
+
+def gpu_run(case, steps, variant=None, **over):
+    from paper_2207_09431_amd.pflbm import Solver
+    prm = dict(case["params"]); prm.update(over)
+    s = Solver(prm)
+    if variant is not None:
+        s.set_variant(variant)
+    s.init_fields(0, case["C"], case.get("u"), case.get("p"))
+    if steps:
+        s.step(steps)
+    m = s.macroscopic(0)
+    s.synchronize()
+    return s, {k: v.cpu().numpy().astype(np.float64) for k, v in m.items()}
+
+
+def compare(m, o, tol=TOL, ptol=None):
+    ru = rel_l2(m["u"], o["u"])
+    rc = rel_l2(m["phi"], o["phi"])
+    print(f"rel-L2 u {ru:.3e}  C {rc:.3e}  p {rel_l2(m['p'], o['p']):.3e}", flush=True)
+    assert ru <= tol and rc <= tol, (ru, rc)
+    if ptol is not None:
+        assert rel_l2(m["p"], o["p"]) <= ptol
+
+
+def test_init_roundtrip(torch):
+    case = inputs.many_bubbles_crop()
+    case["u"] = inputs.velocity_noise(256, 512, 7, 1e-3)
+    case["p"] = inputs.hydrostatic_pressure(case["C"], case["params"]) + inputs.uniform(8, 256 * 512, -1e-5, 1e-5).reshape(512, 256)
+    s, m = gpu_run(case, 0)
+    assert rel_l2(m["u"], case["u"]) < 1e-6
+    assert rel_l2(m["p"], case["p"]) < 1e-6
+    assert np.abs(m["phi"] - case["C"]).max() < 1e-7
+
+
+@pytest.mark.parametrize("steps", [100, 2000])
+def test_rising_bubble_small(torch, steps):
+    case = inputs.rising_bubble_small()
+    print(f"case {case['name']} steps {steps}", flush=True)
+    s, m = gpu_run(case, steps)
+    o = run_case(case, steps).macroscopic()
+    compare(m, o, ptol=1e-4)
+
+
+def test_variants_bitwise_equal_and_ragged(torch):
+    case = inputs.static_bubble(nx=70, ny=45, radius=12.0)
+    o = run_case(case, 60).macroscopic()
+    from paper_2207_09431_amd.pflbm import Solver
+    ref = None
+    nvar = len(Solver(case["params"]).variants())
+    for v in range(nvar):
+        print(f"variant {v}", flush=True)
+        s, m = gpu_run(case, 60, variant=v)
+        compare(m, o)
+        if ref is None:
+            ref = m
+        else:
+            assert np.array_equal(m["u"], ref["u"]) and np.array_equal(m["phi"], ref["phi"])
+
+
+def test_tiny_domain(torch):
+    case = inputs.static_bubble(nx=5, ny=7, radius=1.5, density_ratio=10.0)
+    s, m = gpu_run(case, 20)
+    o = run_case(case, 20).macroscopic()
+    compare(m, o)
+
+
+def test_three_component(torch):
+    case = inputs.three_component(nx=96, ny=192)
+    s, m = gpu_run(case, 100)
+    o = run_case(case, 100).macroscopic()
+    compare(m, o)
+
+
+def test_stored_hbar_at_half(torch):
+    case = inputs.rising_bubble_small()
+    s, m = gpu_run(case, 200, store_h=1)
+    compare(m, run_case(case, 200).macroscopic())
+
+
+def test_stored_hbar_other_tau_h(torch):
+    case = inputs.rising_bubble_small()
+    s, m = gpu_run(case, 100, store_h=1, tau_h=0.8)
+    prm = dict(case["params"]); prm.update(tau_h=0.8)
+    o = Oracle(prm)
+    o.init_fields(case["C"], case["u"], case["p"])
+    o.step(100)
+    compare(m, o.macroscopic())
+
+
+def test_variable_mobility_short(torch):
+    case = inputs.rising_bubble_small()
+    s, m = gpu_run(case, 30, variable_mobility=1)
+    prm = dict(case["params"]); prm.update(variable_mobility=1)
+    o = Oracle(prm)
+    o.init_fields(case["C"], case["u"], case["p"])
+    o.step(30)
+    compare(m, o.macroscopic())
+
+
+# At density ratio 1000 a bubble at rest carries only spurious currents, and
+# u in the gas is the small difference of 3 sum e gbar and F/2 (they cancel to
+# about 1%), which amplifies float32 rounding by about 100: the velocity bound
+# is 3e-5 there, C keeps 1e-5.
+TOL_U_SPURIOUS = 3e-5
+
+
+def test_powerlaw_bubble(torch):
+    case = inputs.powerlaw_bubble(n=0.5, nx=100, ny=200, d=50.0)
+    s, m = gpu_run(case, 300)
+    o = run_case(case, 300).macroscopic()
+    ru = rel_l2(m["u"], o["u"])
+    print(f"rel-L2 u {ru:.3e}", flush=True)
+    assert ru <= TOL_U_SPURIOUS
+    assert rel_l2(m["phi"], o["phi"]) <= TOL
+
+
+@pytest.mark.parametrize("n", [0.5, 1.5])
+def test_powerlaw_channel(torch, n):
+    """Rheology in a real shear flow: power-law liquid between the walls,
+    driven by a body force (shear rates far from the truncation)."""
+    K = {0.5: 0.0025, 1.5: 4.0}[n]
+    L = 16.0
+    G = K * (0.01 * (n + 1) / n / L ** ((n + 1) / n)) ** n
+    case = inputs.channel(n, ny=32, nx=8, fx=G, K=K, nu_min=1e-3, nu_max=1.0)
+    s, m = gpu_run(case, 2000)
+    o = run_case(case, 2000).macroscopic()
+    compare(m, o)
+
+
+def test_centroid_velocity(torch):
+    case = inputs.rising_bubble_small()
+    s, m = gpu_run(case, 200)
+    o = run_case(case, 200)
+    for comp in (0, 2):
+        g = s.bubble_centroid_velocity(0, comp)
+        r = o.centroid(comp)
+        assert abs(g[0] / r[0] - 1) < 1e-6
+        assert abs(g[1] / r[1] - 1) < 1e-4
+        assert np.abs(g[2:4] - r[2:4]).max() < 1e-6 * 128
+        assert np.abs(g[4:6] - r[4:6]).max() < 1e-5 * np.abs(r[4:6]).max() + 1e-12
+
+
+def test_checkpoint_restart_is_bitwise(torch):
+    case = inputs.rising_bubble_small()
+    s, _ = gpu_run(case, 10)
+    snap = s.get_state()
+    s.step(15)
+    a = s.macroscopic(0)["u"].cpu().numpy()
+    s.set_state(snap)
+    s.step(15)
+    b = s.macroscopic(0)["u"].cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_two_runs_bitwise_equal(torch):
+    case = inputs.rising_bubble_small()
+    _, a = gpu_run(case, 40)
+    _, b = gpu_run(case, 40)
+    assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["p"], b["p"])
+
+
+def test_error_paths(torch):
+    from paper_2207_09431_amd.pflbm import Solver, PflbmError
+    case = inputs.rising_bubble_small()
+    s = Solver(case["params"])
+    with pytest.raises(PflbmError) as e:
+        s.step(1)
+    assert e.value.status == -5
+    bad = case["C"].copy()
+    bad[0, 3, 3] = np.nan
+    with pytest.raises(PflbmError) as e:
+        s.init_fields(0, bad)
+    assert e.value.status == -4
+    with pytest.raises(PflbmError) as e:
+        Solver(dict(case["params"], nx=3))
+    assert e.value.status == -1

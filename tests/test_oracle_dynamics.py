@@ -22,6 +22,7 @@ from helpers import rel_l2
 def test_init_roundtrip_ratio_1000():
     case = inputs.many_bubbles_crop()
     case["u"] = inputs.velocity_noise(256, 512, 7, 1e-3)
+    case["p"] = inputs.hydrostatic_pressure(case["C"], case["params"]) + inputs.uniform(8, 256 * 512, -1e-5, 1e-5).reshape(512, 256)
     o = run_case(case, 0)
     m = o.macroscopic()
     assert np.abs(m["u"] - case["u"]).max() < 1e-14
