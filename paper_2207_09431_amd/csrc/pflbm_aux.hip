@@ -28,25 +28,27 @@ struct NodeStencil {
 template <class Get>
 __device__ __forceinline__ NodeStencil stencil_at(const CaseDev& cd, int x, int y, Get get) {
     NodeStencil n;
-    double c1, c2;
-    get(x, y, c1, c2);
-    n.c[0] = (float)c1;
-    n.c[1] = (float)c2;
-    n.rho = mix_rho(cd, n.c[0], n.c[1]);
+    double d1, d2;
+    get(x, y, d1, d2);
+    const float c1 = (float)d1, c2 = (float)d2;
+    n.c[0] = c1;
+    n.c[1] = c2;
+    n.rho = mix_rho(cd, c1, c2);
     float sx[2] = {0.f, 0.f}, sy[2] = {0.f, 0.f}, sl[2] = {0.f, 0.f}, rx = 0.f, ry = 0.f;
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
-        double p1, p2, m1, m2;
-        get(wrap_x(x + Lat::ex[a], cd.nx), mirror_y(y + Lat::ey[a], cd.ny), p1, p2);
-        get(wrap_x(x - Lat::ex[a], cd.nx), mirror_y(y - Lat::ey[a], cd.ny), m1, m2);
+        double q1, q2, r1, r2;
+        get(wrap_x(x + Lat::ex[a], cd.nx), mirror_y(y + Lat::ey[a], cd.ny), q1, q2);
+        get(wrap_x(x - Lat::ex[a], cd.nx), mirror_y(y - Lat::ey[a], cd.ny), r1, r2);
+        const float p1 = (float)q1, p2 = (float)q2, m1 = (float)r1, m2 = (float)r2;
         const float w = Lat::w[a];
-        sx[0] += w * Lat::ex[a] * (float)(p1 - m1);
-        sy[0] += w * Lat::ey[a] * (float)(p1 - m1);
-        sl[0] += w * (float)((p1 - c1) + (m1 - c1));
-        sx[1] += w * Lat::ex[a] * (float)(p2 - m2);
-        sy[1] += w * Lat::ey[a] * (float)(p2 - m2);
-        sl[1] += w * (float)((p2 - c2) + (m2 - c2));
-        const float dr = mix_rho(cd, (float)p1, (float)p2) - mix_rho(cd, (float)m1, (float)m2);
+        sx[0] += w * Lat::ex[a] * (p1 - m1);
+        sy[0] += w * Lat::ey[a] * (p1 - m1);
+        sl[0] += w * ((p1 - c1) + (m1 - c1));
+        sx[1] += w * Lat::ex[a] * (p2 - m2);
+        sy[1] += w * Lat::ey[a] * (p2 - m2);
+        sl[1] += w * ((p2 - c2) + (m2 - c2));
+        const float dr = mix_rho(cd, p1, p2) - mix_rho(cd, m1, m2);
         rx += w * Lat::ex[a] * dr;
         ry += w * Lat::ey[a] * dr;
     }
@@ -57,7 +59,8 @@ __device__ __forceinline__ NodeStencil stencil_at(const CaseDev& cd, int x, int 
     }
     n.grx = 1.5f * rx;
     n.gry = 1.5f * ry;
-    chem_potential_d(cd, c1, c2, n.lc[0], n.lc[1], n.mu);
+    if (cd.n_h == 1) chem_potential<1>(cd, d1, d2, n.lc[0], n.lc[1], n.mu);
+    else chem_potential<2>(cd, d1, d2, n.lc[0], n.lc[1], n.mu);
     return n;
 }
 

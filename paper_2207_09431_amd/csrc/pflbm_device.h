@@ -39,13 +39,13 @@ struct CaseDev {
     int vm;             // variable mobility
     float K, nexp, numin, numax;
     float sig12, sig13, sig23, lam;
-    float Sig[3], SigT;
+    float Sig[3];
     float xi;
     float mob[2];       // D0 / Sigma_i for the carried components
     float omh;          // 1 / (tau_h + 1/2)
     float g, fx;
-    // float64 copies for the bulk chemical potential
-    double dsig12, dsig13, dsig23, dlam, dSig[3], dSigT, dxi;
+    // float64 coefficients of the bulk chemical potential; dA_j = 4 Sigma_T / (xi Sigma_j)
+    double dsig12, dsig13, dsig23, dlam, dSig[3], dA[3];
 };
 
 struct TileDev {
@@ -71,45 +71,52 @@ __device__ __forceinline__ float mix_rho(const CaseDev& cd, float c1, float c2) 
     return cd.rho[0] * clip01(c1) + cd.rho[1] * clip01(c2) + cd.rho[2] * clip01(1.0f - c1 - c2);
 }
 
-// Chemical potentials of the ternary free energy (Sec. 2.1, Eqs. (3), (5)).
-__device__ __forceinline__ void chem_potential(const CaseDev& cd, float c1, float c2, float c3,
-                                               float l1, float l2, float l3, float mu[3]) {
-    const float S0 = cd.Sig[0], S1 = cd.Sig[1], S2 = cd.Sig[2];
-    const float sc = S0 * c1 + S1 * c2 + S2 * c3;
-    const float c123 = c1 * c2 * c3;
-    const float d0 = 2.0f * cd.sig12 * c1 * c2 * c2 + 2.0f * cd.sig13 * c1 * c3 * c3 + c2 * c3 * sc + c123 * S0
-                   + 2.0f * cd.lam * c1 * c2 * c2 * c3 * c3;
-    const float d1 = 2.0f * cd.sig12 * c1 * c1 * c2 + 2.0f * cd.sig23 * c2 * c3 * c3 + c1 * c3 * sc + c123 * S1
-                   + 2.0f * cd.lam * c1 * c1 * c2 * c3 * c3;
-    const float d2 = 2.0f * cd.sig13 * c1 * c1 * c3 + 2.0f * cd.sig23 * c2 * c2 * c3 + c1 * c2 * sc + c123 * S2
-                   + 2.0f * cd.lam * c1 * c1 * c2 * c2 * c3;
-    const float a = 4.0f * cd.SigT / cd.xi, b = 0.75f * cd.xi;
-    mu[0] = a * ((d0 - d1) / S1 + (d0 - d2) / S2) - b * S0 * l1;
-    mu[1] = a * ((d1 - d0) / S0 + (d1 - d2) / S2) - b * S1 * l2;
-    mu[2] = a * ((d2 - d0) / S0 + (d2 - d1) / S1) - b * S2 * l3;
+// Hardware reciprocal (1 ulp), instead of the correctly rounded division
+// sequence: float32 rounding of this size is far below the method's needs.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Global-memory views of the state planes: the pointers come out of the case
+// block, so without the address-space cast the compiler falls back to flat
+// loads and stores.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
 }
 
-// Same potentials with the bulk part evaluated in float64 from float64
-// concentrations: near equilibrium mu is a small difference of the bulk and
-// gradient parts, and float32 concentrations would leave a relative error of
-// order 1e-6 in it.
-__device__ __forceinline__ void chem_potential_d(const CaseDev& cd, double c1, double c2, float l1, float l2,
-                                                 float mu[3]) {
+// Chemical potentials of the ternary free energy (Sec. 2.1, Eqs. (3), (5)):
+// mu_i = sum_{j != i} (dE0/dC_i - dE0/dC_j) a_j - (3/4) xi Sigma_i lap C_i
+// with a_j = 4 Sigma_T / (xi Sigma_j).  The bulk part is evaluated in float64
+// from the float64 concentrations: near equilibrium mu is a small difference
+// of the bulk and gradient parts, and its float32 error reaches the gas
+// velocity amplified by the density ratio.  With one phase field (C_2 = 0)
+// only mu_1 and mu_3 enter the step; the terms that vanish with C_2 are left
+// out, which changes no rounding.
+template <int NH>
+__device__ __forceinline__ void chem_potential(const CaseDev& cd, double c1, double c2, float l1, float l2,
+                                               float mu[3]) {
     const double c3 = 1.0 - c1 - c2;
-    const double S0 = cd.dSig[0], S1 = cd.dSig[1], S2 = cd.dSig[2];
-    const double sc = S0 * c1 + S1 * c2 + S2 * c3;
-    const double c123 = c1 * c2 * c3;
-    const double d0 = 2.0 * cd.dsig12 * c1 * c2 * c2 + 2.0 * cd.dsig13 * c1 * c3 * c3 + c2 * c3 * sc + c123 * S0
-                    + 2.0 * cd.dlam * c1 * c2 * c2 * c3 * c3;
-    const double d1 = 2.0 * cd.dsig12 * c1 * c1 * c2 + 2.0 * cd.dsig23 * c2 * c3 * c3 + c1 * c3 * sc + c123 * S1
-                    + 2.0 * cd.dlam * c1 * c1 * c2 * c3 * c3;
-    const double d2 = 2.0 * cd.dsig13 * c1 * c1 * c3 + 2.0 * cd.dsig23 * c2 * c2 * c3 + c1 * c2 * sc + c123 * S2
-                    + 2.0 * cd.dlam * c1 * c1 * c2 * c2 * c3;
-    const double a = 4.0 * cd.dSigT / cd.dxi;
     const float b = 0.75f * cd.xi;
-    mu[0] = (float)(a * ((d0 - d1) / S1 + (d0 - d2) / S2)) - b * cd.Sig[0] * l1;
-    mu[1] = (float)(a * ((d1 - d0) / S0 + (d1 - d2) / S2)) - b * cd.Sig[1] * l2;
-    mu[2] = (float)(a * ((d2 - d0) / S0 + (d2 - d1) / S1)) + b * cd.Sig[2] * (l1 + l2);
+    if (NH == 1) {
+        const double d0 = 2.0 * cd.dsig13 * c1 * c3 * c3;
+        const double d1 = c1 * c3 * (cd.dSig[0] * c1 + cd.dSig[2] * c3);
+        const double d2 = 2.0 * cd.dsig13 * c1 * c1 * c3;
+        mu[0] = (float)((d0 - d1) * cd.dA[1] + (d0 - d2) * cd.dA[2]) - b * cd.Sig[0] * l1;
+        mu[1] = 0.0f;
+        mu[2] = (float)((d2 - d0) * cd.dA[0] + (d2 - d1) * cd.dA[1]) + b * cd.Sig[2] * l1;
+    } else {
+        const double S0 = cd.dSig[0], S1 = cd.dSig[1], S2 = cd.dSig[2];
+        const double sc = S0 * c1 + S1 * c2 + S2 * c3;
+        const double c123 = c1 * c2 * c3;
+        const double d0 = 2.0 * cd.dsig12 * c1 * c2 * c2 + 2.0 * cd.dsig13 * c1 * c3 * c3 + c2 * c3 * sc + c123 * S0
+                        + 2.0 * cd.dlam * c1 * c2 * c2 * c3 * c3;
+        const double d1 = 2.0 * cd.dsig12 * c1 * c1 * c2 + 2.0 * cd.dsig23 * c2 * c3 * c3 + c1 * c3 * sc + c123 * S1
+                        + 2.0 * cd.dlam * c1 * c1 * c2 * c3 * c3;
+        const double d2 = 2.0 * cd.dsig13 * c1 * c1 * c3 + 2.0 * cd.dsig23 * c2 * c2 * c3 + c1 * c2 * sc + c123 * S2
+                        + 2.0 * cd.dlam * c1 * c1 * c2 * c2 * c3;
+        mu[0] = (float)((d0 - d1) * cd.dA[1] + (d0 - d2) * cd.dA[2]) - b * cd.Sig[0] * l1;
+        mu[1] = (float)((d1 - d0) * cd.dA[0] + (d1 - d2) * cd.dA[2]) - b * cd.Sig[1] * l2;
+        mu[2] = (float)((d2 - d0) * cd.dA[0] + (d2 - d1) * cd.dA[1]) + b * cd.Sig[2] * (l1 + l2);
+    }
 }
 
 // Truncated power law, kinematic (Sec. 2.3, Eqs. (31), (33)).

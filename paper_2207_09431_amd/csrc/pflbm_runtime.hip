@@ -236,16 +236,13 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
         double S[3], ST;
         capillary(p, S, &ST);
         for (int j = 0; j < 3; ++j) d.Sig[j] = (float)S[j];
-        d.SigT = (float)ST;
         d.xi = (float)p.xi;
         d.mob[0] = (float)(p.D0 / S[0]);
         d.mob[1] = (float)(p.D0 / S[1]);
         d.omh = (float)(1.0 / (p.tau_h + 0.5));
         d.g = (float)p.g; d.fx = (float)p.fx;
         d.dsig12 = p.sigma12; d.dsig13 = p.sigma13; d.dsig23 = p.sigma23; d.dlam = p.Lambda;
-        for (int j = 0; j < 3; ++j) d.dSig[j] = S[j];
-        d.dSigT = ST;
-        d.dxi = p.xi;
+        for (int j = 0; j < 3; ++j) { d.dSig[j] = S[j]; d.dA[j] = 4.0 * ST / (p.xi * S[j]); }
     }
     hipError_t e = hipMemcpyAsync(c->ws + L.cases_off, c->cd.data(), sizeof(CaseDev) * ncases, hipMemcpyHostToDevice,
                                   c->stream);

@@ -55,12 +55,14 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     const int nx = cd.nx, ny = cd.ny, pitch = cd.pitch;
     const long long plane = cd.plane;
     const int x0 = tile.x0, y0 = tile.y0;
-    const float* __restrict__ Sin = cd.S[par];
-    const double* __restrict__ Cin = cd.C[par];
-    const float* __restrict__ Tin = cd.T[par];
-    float* __restrict__ Sout = cd.S[par ^ 1];
-    double* __restrict__ Cout = cd.C[par ^ 1];
-    float* __restrict__ Tout = cd.T[par ^ 1];
+    const auto Sin = gmem<const float>(cd.S[par]);
+    const auto Cin = gmem<const double>(cd.C[par]);
+    const auto Tin = gmem<const float>(cd.T[par]);
+    const auto Sout = gmem<float>(cd.S[par ^ 1]);
+    const auto Cout = gmem<double>(cd.C[par ^ 1]);
+    const auto Tout = gmem<float>(cd.T[par ^ 1]);
+    const auto Hin = gmem<const float>(cd.H[par]);
+    const auto Hout = gmem<float>(cd.H[par ^ 1]);
     const int tid = threadIdx.x;
 
     // ---------------- phase A: C_i and rho on R3
@@ -84,28 +86,26 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const int i3 = (ry + 1) * W3 + rx + 1;
         const int gyr = y0 - 2 + ry;
         float c[2], gcx[2], gcy[2], lc[2];
-        double cdd[2];
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
             float sx = 0.f, sy = 0.f, sl = 0.f;
-            const double cc = sCd[i][i3];
+            const float cc = sC[i][i3];
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
-                const double fp = sCd[i][i3 + Lat::ey[a] * W3 + Lat::ex[a]];
-                const double fm = sCd[i][i3 - Lat::ey[a] * W3 - Lat::ex[a]];
-                sx += Lat::w[a] * Lat::ex[a] * (float)(fp - fm);
-                sy += Lat::w[a] * Lat::ey[a] * (float)(fp - fm);
-                sl += Lat::w[a] * (float)((fp - cc) + (fm - cc));
+                const float fp = sC[i][i3 + Lat::ey[a] * W3 + Lat::ex[a]];
+                const float fm = sC[i][i3 - Lat::ey[a] * W3 - Lat::ex[a]];
+                sx += Lat::w[a] * Lat::ex[a] * (fp - fm);
+                sy += Lat::w[a] * Lat::ey[a] * (fp - fm);
+                sl += Lat::w[a] * ((fp - cc) + (fm - cc));
             }
-            cdd[i] = cc;
-            c[i] = (float)cc;
+            c[i] = cc;
             gcx[i] = 1.5f * sx;
             gcy[i] = 1.5f * sy;
             lc[i] = 3.0f * sl;
         }
-        if (NH == 1) { c[1] = 0.f; cdd[1] = 0.0; gcx[1] = 0.f; gcy[1] = 0.f; lc[1] = 0.f; }
+        if (NH == 1) { c[1] = 0.f; gcx[1] = 0.f; gcy[1] = 0.f; lc[1] = 0.f; }
         float mu[3];
-        chem_potential_d(cd, cdd[0], cdd[1], lc[0], lc[1], mu);
+        chem_potential<NH>(cd, sCd[0][i3], NH == 2 ? sCd[NH - 1][i3] : 0.0, lc[0], lc[1], mu);
 #pragma unroll
         for (int k = 0; k < 3; ++k) sMu[k][idx] = mu[k];
         if (gyr >= 0 && gyr < ny) {
@@ -130,8 +130,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             // sum_k mu_k grad C_k with grad C_3 = -grad C_1 - grad C_2
             const float fx = (mu[0] - mu[2]) * gcx[0] + (mu[1] - mu[2]) * gcx[1] + rho * cd.fx;
             const float fy = (mu[0] - mu[2]) * gcy[0] + (mu[1] - mu[2]) * gcy[1] - rho * cd.g;
-            const float ux = (3.0f * jx + 0.5f * fx) / rho;
-            const float uy = (3.0f * jy + 0.5f * fy) / rho;
+            const float rr = rcp(rho);
+            const float ux = (3.0f * jx + 0.5f * fx) * rr;
+            const float uy = (3.0f * jy + 0.5f * fy) * rr;
             sUx[idx] = ux;
             sUy[idx] = uy;
             sP[idx] = s + 0.5f * kCs2 * (ux * grx + uy * gry);
@@ -294,10 +295,10 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             pxy += Lat::ex[a] * Lat::ey[a] * ne;
         }
         // shear rate: D = -Pi / (2 (tau_prev + 1/2) rho c_s^4), gdot = sqrt(2 D:D)
-        const float fs = 4.5f / ((tprev + 0.5f) * rho);
+        const float fs = 4.5f * rcp((tprev + 0.5f) * rho);
         const float gdot = fs * sqrtf(2.0f * (pxx * pxx + pyy * pyy + 2.0f * pxy * pxy));
         const float tau = mixture_tau(cd, c[0], c[1], c3, gdot);
-        const float om = 1.0f / (tau + 0.5f);
+        const float om = rcp(tau + 0.5f);
 
         // gbar collision with the mixed-difference forcing
         const float umr = ux * mrx + uy * mry;
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const float ub = ux * bx + uy * by;
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
-            const float kk = c[i] / rc2;
+            const float kk = c[i] * 3.0f * rcp(rho);
             const float Xx = gcx[i] - kk * bx, Xy = gcy[i] - kk * by;
             const float uX = ux * Xx + uy * Xy;
             const float umc = (i == 0) ? um1 : um2;
@@ -391,8 +392,8 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
                     const int sxg = wrap_x(gx - (dir[a] == a ? Lat::ex[a] : 0), nx);
                     const int syg = dir[a] == a ? gyr - Lat::ey[a] : gyr;
                     const long long so = (long long)syg * pitch + sxg;
-                    hv += (1.0f - cd.omh) * cd.H[par][(long long)(i * 9 + dir[a]) * plane + so];
-                    cd.H[par ^ 1][(long long)(i * 9 + a) * plane + off] = hv;
+                    hv += (1.0f - cd.omh) * Hin[(long long)(i * 9 + dir[a]) * plane + so];
+                    Hout[(long long)(i * 9 + a) * plane + off] = hv;
                     csum += hv;
                 }
                 Cout[(long long)i * plane + off] = (double)csum;
@@ -431,10 +432,12 @@ struct StepVariant {
     {TX, TY, NT, {PFLBM_K(TX, TY, 1, false, NT), PFLBM_K(TX, TY, 1, true, NT)}, {nullptr, nullptr}}
 
 static const StepVariant kVariants[] = {
+    PFLBM_V2(32, 16, 512),
     PFLBM_V2(32, 16, 256),
-    PFLBM_V2(64, 8, 256),
     PFLBM_V2(32, 8, 256),
+    PFLBM_V2(64, 8, 512),
     PFLBM_V1(64, 16, 512),
+    PFLBM_V1(64, 16, 1024),
 };
 
 int step_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
