@@ -2,7 +2,10 @@
 
 The library is the product: fused step kernels, auxiliary kernels and the
 C ABI of include/pflbm.h.  Packed float32 instructions are disabled
-(`-target-feature -packed-fp32-ops`); everything else is plain -O3.
+(`-target-feature -packed-fp32-ops`) and multiply-adds are fused only
+within one source expression (`-ffp-contract=on`), so that every kernel
+variant (tile shape) rounds identically and results do not depend on the
+tile shape; everything else is plain -O3.
 """
 import os
 import subprocess
@@ -17,7 +20,7 @@ ARCH = os.environ.get("PFLBM_ARCH", "gfx950")
 
 
 def hipcc_flags():
-    return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+    return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=on",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

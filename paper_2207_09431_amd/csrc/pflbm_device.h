@@ -55,8 +55,10 @@ struct TileDev {
 __device__ __forceinline__ float clip01(float c) { return fminf(fmaxf(c, 0.0f), 1.0f); }
 
 __device__ __forceinline__ int wrap_x(int x, int nx) {
-    x %= nx;
-    return x < 0 ? x + nx : x;
+    // x lies within a few tile widths of [0, nx): no integer division
+    while (x < 0) x += nx;
+    while (x >= nx) x -= nx;
+    return x;
 }
 // Mirror about the walls at y = -1/2 and y = ny - 1/2 (zero normal
 // derivative of the stencil fields); rows farther than ny away are clamped.

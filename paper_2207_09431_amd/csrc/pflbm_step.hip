@@ -23,13 +23,56 @@
 
 namespace pflbm {
 
+// Isotropic central stencils over the four lattice direction pairs on an LDS
+// array with row pitch W: grad f = sum_a w_a e_a [f(x+e_a) - f(x-e_a)] / (2 c_s^2)
+// and lap f = sum_a w_a [f(x+e_a) - 2 f(x) + f(x-e_a)] / c_s^2, each pair
+// (a, opposite of a) contributing once with twice its weight.
+template <int W>
+__device__ __forceinline__ void cd_grad(const float* f, int i, float& gx, float& gy) {
+    const float d1 = f[i + 1] - f[i - 1], d2 = f[i + W] - f[i - W];
+    const float d5 = f[i + W + 1] - f[i - W - 1], d6 = f[i + W - 1] - f[i - W + 1];
+    gx = (1.0f / 3.0f) * d1 + (1.0f / 12.0f) * (d5 - d6);
+    gy = (1.0f / 3.0f) * d2 + (1.0f / 12.0f) * (d5 + d6);
+}
+template <int W>
+__device__ __forceinline__ float cd_lap(const float* f, int i) {
+    const float c = f[i];
+    const float s1 = (f[i + 1] - c) + (f[i - 1] - c), s2 = (f[i + W] - c) + (f[i - W] - c);
+    const float s5 = (f[i + W + 1] - c) + (f[i - W - 1] - c), s6 = (f[i + W - 1] - c) + (f[i - W + 1] - c);
+    return (2.0f / 3.0f) * (s1 + s2) + (1.0f / 6.0f) * (s5 + s6);
+}
+// e_a . v for a compile-time lattice vector (no multiplications by 0 or 1).
+__device__ __forceinline__ float edot(int ex, int ey, float vx, float vy) {
+    if (ex == 0 && ey == 0) return 0.0f;
+    if (ex == 0) return ey > 0 ? vy : -vy;
+    if (ey == 0) return ex > 0 ? vx : -vx;
+    const float t = ex > 0 ? vx : -vx;
+    return ey > 0 ? t + vy : t - vy;
+}
+// Mixed directional derivatives along e_1..e_8 (mean of the central and the
+// second-order biased differences) and the mixed gradient
+// grad^MD f = sum_a w_a e_a d_a f / c_s^2 built from them.
+template <int W>
+__device__ __forceinline__ void md_all(const float* f, int i, float d[9], float& gx, float& gy) {
+    d[0] = 0.0f;
+    const float fc = f[i];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        const int o = Lat::ey[a] * W + Lat::ex[a];
+        d[a] = 0.25f * (-f[i + 2 * o] + 5.0f * f[i + o] - 3.0f * fc - f[i - o]);
+    }
+    const float p5 = d[5] - d[7], p6 = d[6] - d[8];
+    gx = (1.0f / 3.0f) * (d[1] - d[3]) + (1.0f / 12.0f) * (p5 - p6);
+    gy = (1.0f / 3.0f) * (d[2] - d[4]) + (1.0f / 12.0f) * (p5 + p6);
+}
+
 template <int TX, int TY, int NH, bool SH, int NT>
 __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ cases,
                                                   const TileDev* __restrict__ tiles, int ntiles, int par) {
     constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
     constexpr int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;
     constexpr int W1 = TX + 2, H1 = TY + 2, N1 = W1 * H1;
-    constexpr int NMU = 3;
+    constexpr int NMU = NH + 1;      // mu_1 (, mu_2), mu_3
 
     __shared__ float sC[NH][N3];
     __shared__ double sCd[NH][N3];   // the float64 phase field on R3
@@ -85,29 +128,17 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const int ry = idx / W2, rx = idx - ry * W2;
         const int i3 = (ry + 1) * W3 + rx + 1;
         const int gyr = y0 - 2 + ry;
-        float c[2], gcx[2], gcy[2], lc[2];
+        float gcx[2] = {0.f, 0.f}, gcy[2] = {0.f, 0.f}, lc[2] = {0.f, 0.f};
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
-            float sx = 0.f, sy = 0.f, sl = 0.f;
-            const float cc = sC[i][i3];
-#pragma unroll
-            for (int a = 1; a < 9; ++a) {
-                const float fp = sC[i][i3 + Lat::ey[a] * W3 + Lat::ex[a]];
-                const float fm = sC[i][i3 - Lat::ey[a] * W3 - Lat::ex[a]];
-                sx += Lat::w[a] * Lat::ex[a] * (fp - fm);
-                sy += Lat::w[a] * Lat::ey[a] * (fp - fm);
-                sl += Lat::w[a] * ((fp - cc) + (fm - cc));
-            }
-            c[i] = cc;
-            gcx[i] = 1.5f * sx;
-            gcy[i] = 1.5f * sy;
-            lc[i] = 3.0f * sl;
+            cd_grad<W3>(sC[i], i3, gcx[i], gcy[i]);
+            lc[i] = cd_lap<W3>(sC[i], i3);
         }
-        if (NH == 1) { c[1] = 0.f; gcx[1] = 0.f; gcy[1] = 0.f; lc[1] = 0.f; }
         float mu[3];
         chem_potential<NH>(cd, sCd[0][i3], NH == 2 ? sCd[NH - 1][i3] : 0.0, lc[0], lc[1], mu);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) sMu[k][idx] = mu[k];
+        sMu[0][idx] = mu[0];
+        if (NH == 2) sMu[1][idx] = mu[1];
+        sMu[NH][idx] = mu[2];
         if (gyr >= 0 && gyr < ny) {
             const int gx = wrap_x(x0 - 2 + rx, nx);
             const long long off = (long long)gyr * pitch + gx;
@@ -117,19 +148,16 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             const float s = Sin[off];
             const float jx = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
             const float jy = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
-            float grx = 0.f, gry = 0.f;
-#pragma unroll
-            for (int a = 1; a < 9; ++a) {
-                const float df = sR[i3 + Lat::ey[a] * W3 + Lat::ex[a]] - sR[i3 - Lat::ey[a] * W3 - Lat::ex[a]];
-                grx += Lat::w[a] * Lat::ex[a] * df;
-                gry += Lat::w[a] * Lat::ey[a] * df;
-            }
-            grx *= 1.5f;
-            gry *= 1.5f;
+            float grx, gry;
+            cd_grad<W3>(sR, i3, grx, gry);
             const float rho = sR[i3];
             // sum_k mu_k grad C_k with grad C_3 = -grad C_1 - grad C_2
-            const float fx = (mu[0] - mu[2]) * gcx[0] + (mu[1] - mu[2]) * gcx[1] + rho * cd.fx;
-            const float fy = (mu[0] - mu[2]) * gcy[0] + (mu[1] - mu[2]) * gcy[1] - rho * cd.g;
+            float fx = (mu[0] - mu[2]) * gcx[0] + rho * cd.fx;
+            float fy = (mu[0] - mu[2]) * gcy[0] - rho * cd.g;
+            if (NH == 2) {
+                fx += (mu[1] - mu[2]) * gcx[1];
+                fy += (mu[1] - mu[2]) * gcy[1];
+            }
             const float rr = rcp(rho);
             const float ux = (3.0f * jx + 0.5f * fx) * rr;
             const float uy = (3.0f * jy + 0.5f * fy) * rr;
@@ -140,16 +168,18 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     }
     __syncthreads();
     // the two ghost rows beyond each wall mirror the wall rows for grad p
-    // (rows farther out are never read)
-    for (int idx = tid; idx < N2; idx += NT) {
-        const int ry = idx / W2, rx = idx - ry * W2;
-        const int gyr = y0 - 2 + ry;
-        if ((gyr < 0 && gyr >= -2) || (gyr >= ny && gyr < ny + 2)) {
-            const int rm = mirror_y(gyr, ny) - (y0 - 2);
-            sP[idx] = sP[rm * W2 + rx];
+    // (rows farther out are never read); only tiles next to a wall have them
+    if (y0 < 2 || y0 + TY + 2 > ny) {
+        for (int idx = tid; idx < N2; idx += NT) {
+            const int ry = idx / W2, rx = idx - ry * W2;
+            const int gyr = y0 - 2 + ry;
+            if ((gyr < 0 && gyr >= -2) || (gyr >= ny && gyr < ny + 2)) {
+                const int rm = mirror_y(gyr, ny) - (y0 - 2);
+                sP[idx] = sP[rm * W2 + rx];
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     // ---------------- phase C: collisions on R1
     for (int idx = tid; idx < N1; idx += NT) {
@@ -168,132 +198,98 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         d[0] = -(d[1] + d[2] + d[3] + d[4] + d[5] + d[6] + d[7] + d[8]);
         const float tprev = Tin[off];
 
-        float c[2], gcx[2], gcy[2];
+        // central gradients of C_i and rho, moments and potentials of the node
+        float c[2] = {0.f, 0.f}, gcx[2] = {0.f, 0.f}, gcy[2] = {0.f, 0.f};
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
-            float sx = 0.f, sy = 0.f;
-#pragma unroll
-            for (int a = 1; a < 9; ++a) {
-                const float df = sC[i][i3 + Lat::ey[a] * W3 + Lat::ex[a]] - sC[i][i3 - Lat::ey[a] * W3 - Lat::ex[a]];
-                sx += Lat::w[a] * Lat::ex[a] * df;
-                sy += Lat::w[a] * Lat::ey[a] * df;
-            }
             c[i] = sC[i][i3];
-            gcx[i] = 1.5f * sx;
-            gcy[i] = 1.5f * sy;
+            cd_grad<W3>(sC[i], i3, gcx[i], gcy[i]);
         }
-        if (NH == 1) { c[1] = 0.f; gcx[1] = 0.f; gcy[1] = 0.f; }
         const float c3 = 1.0f - c[0] - c[1];
         const float rho = sR[i3];
-        float grx = 0.f, gry = 0.f;
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            const float df = sR[i3 + Lat::ey[a] * W3 + Lat::ex[a]] - sR[i3 - Lat::ey[a] * W3 - Lat::ex[a]];
-            grx += Lat::w[a] * Lat::ex[a] * df;
-            gry += Lat::w[a] * Lat::ey[a] * df;
-        }
-        grx *= 1.5f;
-        gry *= 1.5f;
-
-        float mu[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) mu[k] = sMu[k][i2];
-        const float ux = sUx[i2], uy = sUy[i2], p = sP[i2];
-        float gpx = 0.f, gpy = 0.f;
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            const float df = sP[i2 + Lat::ey[a] * W2 + Lat::ex[a]] - sP[i2 - Lat::ey[a] * W2 - Lat::ex[a]];
-            gpx += Lat::w[a] * Lat::ex[a] * df;
-            gpy += Lat::w[a] * Lat::ey[a] * df;
-        }
-        gpx *= 1.5f;
-        gpy *= 1.5f;
+        float grx, gry, gpx, gpy;
+        cd_grad<W3>(sR, i3, grx, gry);
+        cd_grad<W2>(sP, i2, gpx, gpy);
+        const float mu1 = sMu[0][i2], mu3 = sMu[NH][i2];
+        const float mu2 = NH == 2 ? sMu[1][i2] : 0.0f;
+        const float ux = sUx[i2], uy = sUy[i2];
 
         // diffusion source Dif_i = div(D_i grad mu_i) in the product form of Eq. (21)
-        float dif[2];
+        float dif[2] = {0.f, 0.f};
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
-            float mx = 0.f, my = 0.f, ml = 0.f, sx = 0.f, sy = 0.f;
-            const float mc = sMu[i][i2];
-#pragma unroll
-            for (int a = 1; a < 9; ++a) {
-                const float fp = sMu[i][i2 + Lat::ey[a] * W2 + Lat::ex[a]];
-                const float fm = sMu[i][i2 - Lat::ey[a] * W2 - Lat::ex[a]];
-                mx += Lat::w[a] * Lat::ex[a] * (fp - fm);
-                my += Lat::w[a] * Lat::ey[a] * (fp - fm);
-                ml += Lat::w[a] * ((fp - mc) + (fm - mc));
-            }
-            const float lapmu = 3.0f * ml;
+            float mx, my;
+            cd_grad<W2>(sMu[i], i2, mx, my);
+            const float lapmu = cd_lap<W2>(sMu[i], i2);
             if (cd.vm) {
-#pragma unroll
-                for (int a = 1; a < 9; ++a) {
-                    const float cp = clip01(sC[i][i3 + Lat::ey[a] * W3 + Lat::ex[a]]);
-                    const float cm = clip01(sC[i][i3 - Lat::ey[a] * W3 - Lat::ex[a]]);
-                    const float df = (cp - cp * cp) - (cm - cm * cm);
-                    sx += Lat::w[a] * Lat::ex[a] * df;
-                    sy += Lat::w[a] * Lat::ey[a] * df;
-                }
+                // grad of C_i - C_i^2 with C_i limited to [0, 1]
+                auto sf = [&](int j) { const float q = clip01(sC[i][j]); return q - q * q; };
+                const float e1 = sf(i3 + 1) - sf(i3 - 1), e2 = sf(i3 + W3) - sf(i3 - W3);
+                const float e5 = sf(i3 + W3 + 1) - sf(i3 - W3 - 1), e6 = sf(i3 + W3 - 1) - sf(i3 - W3 + 1);
+                const float sgx = (1.0f / 3.0f) * e1 + (1.0f / 12.0f) * (e5 - e6);
+                const float sgy = (1.0f / 3.0f) * e2 + (1.0f / 12.0f) * (e5 + e6);
                 const float cl = clip01(c[i]);
-                dif[i] = cd.mob[i] * (cl * (1.0f - cl) * lapmu + 2.25f * (sx * mx + sy * my));
+                dif[i] = cd.mob[i] * (cl * (1.0f - cl) * lapmu + (sgx * mx + sgy * my));
             } else {
                 dif[i] = cd.mob[i] * lapmu;
             }
         }
 
-        // mixed directional derivatives along every e_a (radius 2)
-        float drho[9], dc[2][9];
-        drho[0] = 0.f;
-        dc[0][0] = 0.f;
-        dc[1][0] = 0.f;
+        // mixed directional derivatives along every e_a (radius 2) and their gradients
+        float drho[9], dc[2][9], mrx, mry, mcx[2] = {0.f, 0.f}, mcy[2] = {0.f, 0.f};
+        md_all<W3>(sR, i3, drho, mrx, mry);
 #pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            const int o1 = Lat::ey[a] * W3 + Lat::ex[a];
-            drho[a] = 0.25f * (-sR[i3 + 2 * o1] + 5.0f * sR[i3 + o1] - 3.0f * sR[i3] - sR[i3 - o1]);
+        for (int i = 0; i < NH; ++i) md_all<W3>(sC[i], i3, dc[i], mcx[i], mcy[i]);
+        if (NH == 1) {
 #pragma unroll
-            for (int i = 0; i < NH; ++i)
-                dc[i][a] = 0.25f * (-sC[i][i3 + 2 * o1] + 5.0f * sC[i][i3 + o1] - 3.0f * sC[i][i3] - sC[i][i3 - o1]);
-            if (NH == 1) dc[1][a] = 0.f;
+            for (int a = 0; a < 9; ++a) dc[1][a] = 0.0f;
         }
-        float mrx = 0.f, mry = 0.f, m1x = 0.f, m1y = 0.f, m2x = 0.f, m2y = 0.f;
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            mrx += Lat::w[a] * Lat::ex[a] * drho[a];
-            mry += Lat::w[a] * Lat::ey[a] * drho[a];
-            m1x += Lat::w[a] * Lat::ex[a] * dc[0][a];
-            m1y += Lat::w[a] * Lat::ey[a] * dc[0][a];
-            m2x += Lat::w[a] * Lat::ex[a] * dc[1][a];
-            m2y += Lat::w[a] * Lat::ey[a] * dc[1][a];
-        }
-        mrx *= 3.0f; mry *= 3.0f; m1x *= 3.0f; m1y *= 3.0f; m2x *= 3.0f; m2y *= 3.0f;
 
         // force, equilibria (deviation form) and the non-equilibrium second moment
-        const float mu13 = mu[0] - mu[2], mu23 = mu[1] - mu[2];
+        const float mu13 = mu1 - mu3, mu23 = mu2 - mu3;
         const float fbx = rho * cd.fx, fby = -rho * cd.g;
-        const float Fx = mu13 * gcx[0] + mu23 * gcx[1] + fbx;
-        const float Fy = mu13 * gcy[0] + mu23 * gcy[1] + fby;
+        float Fx = mu13 * gcx[0] + fbx, Fy = mu13 * gcy[0] + fby;
+        if (NH == 2) {
+            Fx += mu23 * gcx[1];
+            Fy += mu23 * gcy[1];
+        }
         const float uu = ux * ux + uy * uy;
         const float ugr = ux * grx + uy * gry;
         const float uF = ux * Fx + uy * Fy;
         const float ps = 0.5f * kCs2 * ugr;          // p - s
         const float rc2 = rho * kCs2;
-        float A[9], deq[9];
+        float wA[9], G[9], deq[9];
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            const float eu = Lat::ex[a] * ux + Lat::ey[a] * uy;
-            A[a] = 3.0f * eu + 4.5f * eu * eu - 1.5f * uu;     // Gamma_a / w_a - 1
-            const float egr = Lat::ex[a] * grx + Lat::ey[a] * gry - ugr;
-            const float eF = Lat::ex[a] * Fx + Lat::ey[a] * Fy - uF;
+            const int ex = Lat::ex[a], ey = Lat::ey[a];
             const float wa = Lat::w[a];
-            deq[a] = wa * ps + rc2 * wa * A[a] - 0.5f * (kCs2 * egr * wa * A[a] + eF * wa * (1.0f + A[a]));
+            const float eu = edot(ex, ey, ux, uy);
+            const float A = 3.0f * eu + 4.5f * eu * eu - 1.5f * uu;   // Gamma_a / w_a - 1
+            wA[a] = wa * A;
+            G[a] = wa + wA[a];
+            const float egr = edot(ex, ey, grx, gry) - ugr;
+            const float eF = edot(ex, ey, Fx, Fy) - uF;
+            deq[a] = wa * ps + wA[a] * (rc2 - 0.5f * kCs2 * egr) - 0.5f * eF * G[a];
         }
-        float pxx = 0.f, pyy = 0.f, pxy = 0.f;
+        // non-equilibrium part; its zeroth and first moments vanish exactly
+        // (u and p are the moments of this gbar), so the float32 rounding left
+        // in them is projected out: the collision then conserves the pressure
+        // and momentum moments to the rounding of small numbers instead of
+        // leaking a systematic residue every step
+        float ne[9];
 #pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            const float ne = d[a] - deq[a];
-            pxx += Lat::ex[a] * Lat::ex[a] * ne;
-            pyy += Lat::ey[a] * Lat::ey[a] * ne;
-            pxy += Lat::ex[a] * Lat::ey[a] * ne;
+        for (int a = 0; a < 9; ++a) ne[a] = d[a] - deq[a];
+        {
+            const float m0 = ((ne[0] + ne[1]) + (ne[2] + ne[3])) + ((ne[4] + ne[5]) + (ne[6] + ne[7])) + ne[8];
+            const float mx = (ne[1] - ne[3]) + ((ne[5] - ne[7]) + (ne[8] - ne[6]));
+            const float my = (ne[2] - ne[4]) + ((ne[5] - ne[7]) + (ne[6] - ne[8]));
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+                ne[a] -= Lat::w[a] * (m0 + 3.0f * edot(Lat::ex[a], Lat::ey[a], mx, my));
         }
+        const float pdiag = ne[5] + ne[6] + ne[7] + ne[8];
+        const float pxx = ne[1] + ne[3] + pdiag, pyy = ne[2] + ne[4] + pdiag;
+        const float pxy = ne[5] - ne[6] + ne[7] - ne[8];
         // shear rate: D = -Pi / (2 (tau_prev + 1/2) rho c_s^4), gdot = sqrt(2 D:D)
         const float fs = 4.5f * rcp((tprev + 0.5f) * rho);
         const float gdot = fs * sqrtf(2.0f * (pxx * pxx + pyy * pyy + 2.0f * pxy * pxy));
@@ -302,16 +298,14 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
 
         // gbar collision with the mixed-difference forcing
         const float umr = ux * mrx + uy * mry;
-        const float um1 = ux * m1x + uy * m1y, um2 = ux * m2x + uy * m2y;
+        const float um1 = ux * mcx[0] + uy * mcy[0], um2 = ux * mcx[1] + uy * mcy[1];
         const float ufb = ux * fbx + uy * fby;
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            const float wa = Lat::w[a];
-            const float t1 = kCs2 * (drho[a] - umr) * wa * A[a];
-            const float t2 = mu13 * (dc[0][a] - um1) + mu23 * (dc[1][a] - um2)
-                           + (Lat::ex[a] * fbx + Lat::ey[a] * fby - ufb);
-            const float Fa = t1 + t2 * wa * (1.0f + A[a]);
-            sD[a][idx] = d[a] - om * (d[a] - deq[a]) + Fa;
+            const float t1 = kCs2 * (drho[a] - umr) * wA[a];
+            float t2 = mu13 * (dc[0][a] - um1) + (edot(Lat::ex[a], Lat::ey[a], fbx, fby) - ufb);
+            if (NH == 2) t2 += mu23 * (dc[1][a] - um2);
+            sD[a][idx] = d[a] - om * ne[a] + (t1 + t2 * G[a]);
         }
         sS[idx] = s;
 
@@ -319,28 +313,28 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         // mixed derivative of C_i and central grad p, source half of Dif
         const float bx = gpx - Fx, by = gpy - Fy;
         const float ub = ux * bx + uy * by;
+        const float r3 = 3.0f * rcp(rho);
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
-            const float kk = c[i] * 3.0f * rcp(rho);
+            const float kk = c[i] * r3;                // C_i / (rho c_s^2)
             const float Xx = gcx[i] - kk * bx, Xy = gcy[i] - kk * by;
             const float uX = ux * Xx + uy * Xy;
             const float umc = (i == 0) ? um1 : um2;
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
-                const float G = Lat::w[a] * (1.0f + A[a]);
-                const float eX = Lat::ex[a] * Xx + Lat::ey[a] * Xy - uX;
-                const float fX = (dc[i][a] - umc) - kk * (Lat::ex[a] * bx + Lat::ey[a] * by - ub);
+                const int ex = Lat::ex[a], ey = Lat::ey[a];
+                const float eX = edot(ex, ey, Xx, Xy) - uX;
+                const float fX = (dc[i][a] - umc) - kk * (edot(ex, ey, bx, by) - ub);
                 if (SH) {
-                    const float heq = c[i] * G - 0.5f * eX * G;
-                    sH[i][a][idx] = cd.omh * heq + fX * G + 0.5f * dif[i] * G;
+                    const float heq = c[i] * G[a] - 0.5f * eX * G[a];
+                    sH[i][a][idx] = cd.omh * heq + fX * G[a] + 0.5f * dif[i] * G[a];
                 } else {
                     // omega_h = 1: hbar* - w_a C = w_a A_a C + (-(e-u).X/2 + (e-u).X^MD + Dif/2) Gamma_a
-                    sH[i][a][idx] = Lat::w[a] * A[a] * c[i] + (-0.5f * eX + fX + 0.5f * dif[i]) * G;
+                    sH[i][a][idx] = wA[a] * c[i] + (-0.5f * eX + fX + 0.5f * dif[i]) * G[a];
                 }
             }
             sDif[i][idx] = dif[i];
         }
-        (void)p;
         // tau is written for the tile's own nodes
         const int ox = rx - 1, oy = ry - 1;
         if (ox >= 0 && ox < TX && oy >= 0 && oy < TY && x0 + ox < nx) Tout[off] = tau;
@@ -355,7 +349,6 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const int i1 = (oy + 1) * W1 + ox + 1;
         const int i2 = (oy + 2) * W2 + ox + 2;
         const long long off = (long long)gyr * pitch + gx;
-        const float ux = sUx[i2], uy = sUy[i2], uu = ux * ux + uy * uy;
         float sv[9], dv[9];
         int src[9], dir[9];
 #pragma unroll
@@ -364,15 +357,19 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             if (sy < 0 || sy >= ny) { src[a] = i1; dir[a] = Lat::opp[a]; }
             else { src[a] = i1 - Lat::ey[a] * W1 - Lat::ex[a]; dir[a] = a; }
         }
-        float snew = 0.f, dsum = 0.f;
+        // s(y) = sum_a w_a s(z_a) + sum_a d*_a(z_a), formed around the node's own
+        // s with sum_a w_a = 1 taken exactly (the float32 weights sum to
+        // 1 + 8e-9, which would inflate the pressure level every step)
+        const float sy0 = sS[i1];
+        float ssum = 0.f, dsum = 0.f;
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             sv[a] = sS[src[a]];
             dv[a] = sD[dir[a]][src[a]];
-            snew += Lat::w[a] * sv[a];
+            if (a > 0 && dir[a] == a) ssum += Lat::w[a] * (sv[a] - sy0);
             dsum += dv[a];
         }
-        snew += dsum;
+        const float snew = sy0 + (ssum + dsum);
         Sout[off] = snew;
 #pragma unroll
         for (int a = 1; a < 9; ++a) Sout[a * plane + off] = Lat::w[a] * (sv[a] - snew) + dv[a];
@@ -383,6 +380,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         for (int i = 0; i < NH; ++i) {
             const float hd = 0.5f * sDif[i][i1];
             if (SH) {
+                const float ux = sUx[i2], uy = sUy[i2], uu = ux * ux + uy * uy;
                 float csum = 0.f;
 #pragma unroll
                 for (int a = 0; a < 9; ++a) {
@@ -399,17 +397,16 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
                 Cout[(long long)i * plane + off] = (double)csum;
             } else {
                 // C(t+1) = C(y) + sum_a [w_a (C(z_a) - C(y)) + (hbar*_b(z_a) - w_b C(z_a))] + Dif(y)/2 sum_a Gamma_a(y)
+                // (sum_a Gamma_a = 1 exactly for D2Q9)
                 const double cy = sCd[i][j3];
                 double dsum = 0.0;
-                float qsum = 0.f, gsum = 0.f;
+                float qsum = 0.f;
 #pragma unroll
                 for (int a = 0; a < 9; ++a) {
-                    const float eu = Lat::ex[a] * ux + Lat::ey[a] * uy;
-                    gsum += Lat::w[a] * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
                     qsum += sH[i][dir[a]][src[a]];
-                    if (dir[a] == a) dsum += (double)Lat::w[a] * (sCd[i][j3 - Lat::ey[a] * W3 - Lat::ex[a]] - cy);
+                    if (a > 0 && dir[a] == a) dsum += (double)Lat::w[a] * (sCd[i][j3 - Lat::ey[a] * W3 - Lat::ex[a]] - cy);
                 }
-                Cout[(long long)i * plane + off] = cy + (dsum + (double)(qsum + hd * gsum));
+                Cout[(long long)i * plane + off] = cy + (dsum + (double)(qsum + hd));
             }
         }
     }
