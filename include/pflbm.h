@@ -151,6 +151,25 @@ int32_t pflbm_num_variants(const pflbm_ctx* ctx);
 const char* pflbm_variant_name(const pflbm_ctx* ctx, int32_t index);
 int32_t pflbm_set_variant(pflbm_ctx* ctx, int32_t index);
 
+/*
+ * Times every variant on the current state for `steps` launches each and
+ * selects the fastest for pflbm_step.  The state is left unchanged (each
+ * timed launch recomputes the same step into the spare buffer).  `best`
+ * receives the chosen index; `ms_per_variant` (NULL or pflbm_num_variants
+ * floats) receives the mean milliseconds per step, -1 for a variant that does
+ * not apply.  Synchronises the stream.  Errors: STATE before init_fields.
+ */
+int32_t pflbm_autotune(pflbm_ctx* ctx, int32_t steps, int32_t* best, float* ms_per_variant);
+
+/*
+ * Launch mode of pflbm_step: 0 launches every step separately; an even
+ * steps_per_graph > 0 captures that many steps once into a hipGraph and
+ * replays it (whole graphs first, single launches for the remainder).  The
+ * graph is rebuilt when the variant changes.  Results are identical to plain
+ * launches.
+ */
+int32_t pflbm_set_graph(pflbm_ctx* ctx, int32_t steps_per_graph);
+
 /* Stream of the step kernel (hipStream_t as void*), for timing with events. */
 void* pflbm_stream(const pflbm_ctx* ctx);
 

@@ -152,6 +152,10 @@ struct pflbm_ctx {
     int variant = 0;
     int ntiles = 0;
     int device = 0;
+    // replay of a captured pair of steps (parity 0 -> 1 -> 0)
+    int graph_steps = 0;                 // 0: plain launches
+    hipGraphExec_t graph = nullptr;
+    int graph_variant = -1;
 };
 
 namespace {
@@ -276,18 +280,107 @@ int32_t pflbm_init_fields(pflbm_ctx* c, int32_t k, const double* C, const double
     return PFLBM_OK;
 }
 
+static hipError_t launch_one(pflbm_ctx* c, int par) {
+    const CaseDev* cases = dev_case(c, 0);
+    const TileDev* tiles = reinterpret_cast<const TileDev*>(c->ws + c->L.tiles_off);
+    return launch_step(c->variant, c->prm[0].n_h, c->prm[0].store_h != 0, cases, tiles, c->ntiles, par, c->stream);
+}
+
+static void drop_graph(pflbm_ctx* c) {
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    c->graph_variant = -1;
+}
+
+// Captures graph_steps launches (an even number, parities alternating from 0)
+// on a private capture of the context's stream.
+static int32_t build_graph(pflbm_ctx* c) {
+    drop_graph(c);
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return PFLBM_ERR_DEVICE;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    hipStream_t saved = c->stream;
+    c->stream = cs;
+    for (int k = 0; e == hipSuccess && k < c->graph_steps; ++k) e = launch_one(c, k & 1);
+    c->stream = saved;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) { c->graph = nullptr; return PFLBM_ERR_DEVICE; }
+    c->graph_variant = c->variant;
+    return PFLBM_OK;
+}
+
 int32_t pflbm_step(pflbm_ctx* c, int64_t nsteps) {
     if (!c || nsteps < 0) return PFLBM_ERR_INVALID_ARG;
     if (!all_init(c)) return PFLBM_ERR_STATE;
-    const CaseDev* cases = dev_case(c, 0);
-    const TileDev* tiles = reinterpret_cast<const TileDev*>(c->ws + c->L.tiles_off);
-    for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_step(c->variant, c->prm[0].n_h, c->prm[0].store_h != 0, cases, tiles, c->ntiles,
-                                   c->par, c->stream);
-        if (e != hipSuccess) return PFLBM_ERR_DEVICE;
+    int64_t s = 0;
+    if (c->graph_steps > 0 && nsteps >= c->graph_steps) {
+        if (!c->graph || c->graph_variant != c->variant) {
+            int32_t st = build_graph(c);
+            if (st != PFLBM_OK) return st;
+        }
+        // the graph starts from parity 0: bring the state there first
+        if (c->par != 0) {
+            if (launch_one(c, c->par) != hipSuccess) return PFLBM_ERR_DEVICE;
+            c->par ^= 1;
+            ++s;
+        }
+        for (; s + c->graph_steps <= nsteps; s += c->graph_steps)
+            if (hipGraphLaunch(c->graph, c->stream) != hipSuccess) return PFLBM_ERR_DEVICE;
+    }
+    for (; s < nsteps; ++s) {
+        if (launch_one(c, c->par) != hipSuccess) return PFLBM_ERR_DEVICE;
         c->par ^= 1;
     }
     return PFLBM_OK;
+}
+
+int32_t pflbm_set_graph(pflbm_ctx* c, int32_t steps_per_graph) {
+    if (!c || steps_per_graph < 0 || (steps_per_graph & 1)) return PFLBM_ERR_INVALID_ARG;
+    drop_graph(c);
+    c->graph_steps = steps_per_graph;
+    return PFLBM_OK;
+}
+
+int32_t pflbm_autotune(pflbm_ctx* c, int32_t steps, int32_t* best, float* ms_per_variant) {
+    if (!c || steps <= 0) return PFLBM_ERR_INVALID_ARG;
+    if (!all_init(c)) return PFLBM_ERR_STATE;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return PFLBM_ERR_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return PFLBM_ERR_DEVICE; }
+    int bestv = -1;
+    float bestms = 0.f;
+    int32_t st = PFLBM_OK;
+    for (int v = 0; v < step_variant_count() && st == PFLBM_OK; ++v) {
+        int tx, ty, nt;
+        if (ms_per_variant) ms_per_variant[v] = -1.0f;
+        if (!step_variant_shape(v, c->prm[0].n_h, &tx, &ty, &nt)) continue;
+        st = build_tiles(c, v);
+        if (st != PFLBM_OK) break;
+        // every launch reads the current parity and writes the other buffer:
+        // the state is left as it was
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = launch_one(c, c->par);
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int k = 0; k < steps && e == hipSuccess; ++k) e = launch_one(c, c->par);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { st = PFLBM_ERR_DEVICE; break; }
+        ms /= (float)steps;
+        if (ms_per_variant) ms_per_variant[v] = ms;
+        if (bestv < 0 || ms < bestms) { bestv = v; bestms = ms; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != PFLBM_OK) return st;
+    if (best) *best = bestv;
+    return build_tiles(c, bestv);
 }
 
 int32_t pflbm_macroscopic(pflbm_ctx* c, int32_t k, float* rho, float* u, float* p, float* phi) {
@@ -387,6 +480,7 @@ double pflbm_bytes_per_update(const pflbm_ctx* c) {
 
 int32_t pflbm_destroy(pflbm_ctx* c) {
     if (!c) return PFLBM_ERR_INVALID_ARG;
+    drop_graph(c);
     const hipError_t e = hipStreamSynchronize(c->stream);
     delete c;
     if (e != hipSuccess) return PFLBM_ERR_DEVICE;

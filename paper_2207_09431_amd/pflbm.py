@@ -22,7 +22,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "device", -4: "n
 EXPORTS = ("pflbm_workspace_bytes", "pflbm_create", "pflbm_init_fields", "pflbm_step", "pflbm_macroscopic",
            "pflbm_bubble_centroid_velocity", "pflbm_state_bytes", "pflbm_get_state", "pflbm_set_state",
            "pflbm_export_populations", "pflbm_num_variants", "pflbm_variant_name", "pflbm_set_variant",
-           "pflbm_stream", "pflbm_bytes_per_update", "pflbm_destroy", "pflbm_status_string")
+           "pflbm_autotune", "pflbm_set_graph", "pflbm_stream", "pflbm_bytes_per_update", "pflbm_destroy",
+           "pflbm_status_string")
 
 
 class PflbmError(RuntimeError):
@@ -93,6 +94,10 @@ def lib():
         L.pflbm_variant_name.restype = ct.c_char_p
         L.pflbm_set_variant.argtypes = [vp, i32]
         L.pflbm_set_variant.restype = i32
+        L.pflbm_autotune.argtypes = [vp, i32, P(i32), P(ct.c_float)]
+        L.pflbm_autotune.restype = i32
+        L.pflbm_set_graph.argtypes = [vp, i32]
+        L.pflbm_set_graph.restype = i32
         L.pflbm_stream.argtypes = [vp]
         L.pflbm_stream.restype = vp
         L.pflbm_bytes_per_update.argtypes = [vp]
@@ -213,6 +218,44 @@ class Solver:
 
     def set_variant(self, index):
         _check("pflbm_set_variant", lib().pflbm_set_variant(self._h, int(index)))
+
+    def autotune(self, steps=10, cache=None):
+        """Pick the fastest tile variant for these cases on this GPU.  With a
+        `cache` path (JSON), a previous choice for the same case shapes is
+        reused instead of timing again.  Returns the chosen variant name."""
+        import json
+        key = None
+        names = self.variants()
+        if cache is not None:
+            import torch
+            dev = torch.cuda.get_device_properties(self.device).name
+            key = json.dumps([dev, [(p["nx"], p["ny"], p["n_h"], p.get("store_h", 0), p.get("storage", 0))
+                                    for p in self.params]])
+            try:
+                table = json.load(open(cache))
+            except (OSError, ValueError):
+                table = {}
+            if key in table and table[key] in names:
+                self.set_variant(names.index(table[key]))
+                return table[key]
+        n = len(names)
+        ms = (ct.c_float * n)()
+        best = ct.c_int32(-1)
+        _check("pflbm_autotune", lib().pflbm_autotune(self._h, int(steps), ct.byref(best), ms))
+        self.tuning = {names[i]: float(ms[i]) for i in range(n) if ms[i] >= 0}
+        name = names[best.value]
+        if cache is not None:
+            try:
+                table = json.load(open(cache))
+            except (OSError, ValueError):
+                table = {}
+            table[key] = name
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1)
+        return name
+
+    def set_graph(self, steps_per_graph):
+        _check("pflbm_set_graph", lib().pflbm_set_graph(self._h, int(steps_per_graph)))
 
     def bytes_per_update(self):
         return float(lib().pflbm_bytes_per_update(self._h))
