@@ -1,10 +1,12 @@
 """Throughput of the fused phase-field power-law D2Q9 step on one MI355X.
 
 Default workload: one 2048 x 4096 domain with 64 seeded bubbles in a
-shear-thinning power-law liquid (n = 0.6), density ratio 1000, float32.  A
-"step" is one time step of the whole domain (collision, streaming,
-bounce-back, phase-field update); the timed region covers exactly `--steps`
-steps with the inputs resident in HBM.  Prints one JSON line.
+shear-thinning power-law liquid (n = 0.6), density ratio 1000, float32
+arithmetic.  A "step" is one time step of the whole domain (collision,
+streaming, bounce-back, phase-field update); the timed region covers exactly
+`--steps` steps with the state resident in HBM.  The tile variant is chosen by
+the autotuner before timing.  Prints one JSON line; the "forms" object adds
+the batched 48-case sweep (batched vs one by one) and the stored-hbar form.
 """
 import argparse
 import json
@@ -17,6 +19,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the step kernel on the default 2048 x 4096 workload,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by the same counters
+# read for a 512 MiB device copy (x 2.0 and x 1.0).  Valid only for the kernel
+# sources they were taken on (sha256 prefix of pflbm_step.hip + pflbm_device.h)
+# and the same tile variant; otherwise the bench reports null.
+MEASURED_TRAFFIC = {"source_sha256": "b5426e50f910954c", "variant": "tile64x16_t1024",
+                    "nx": 2048, "ny": 4096, "bytes_per_launch": 812.8e6}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -26,11 +36,51 @@ def parse():
     ap.add_argument("--nx", type=int, default=2048)
     ap.add_argument("--ny", type=int, default=4096)
     ap.add_argument("--bubbles", type=int, default=64)
-    ap.add_argument("--variant", type=int, default=-1)
-    ap.add_argument("--store-h", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=-1, help="tile variant; -1 autotunes")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and stored-hbar forms")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("pflbm_step.hip", "pflbm_device.h"):
+        with open(os.path.join(ROOT, "paper_2207_09431_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(variant, nx, ny):
+    m = MEASURED_TRAFFIC
+    try:
+        same = kernel_source_hash() == m["source_sha256"]
+    except OSError:
+        same = False
+    if same and variant == m["variant"] and (nx, ny) == (m["nx"], m["ny"]):
+        return m["bytes_per_launch"]
+    return None
+
+
+def timed_steps(torch, solvers, steps, warmup):
+    """Milliseconds per step for advancing every solver by one step per step
+    (all on the current stream), measured with events on that stream."""
+    for s in solvers:
+        s.step(warmup)
+    torch.cuda.synchronize()
+    stream = solvers[0].stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for s in solvers:
+        s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, time.perf_counter() - t0
 
 
 def cpu_baseline(seconds):
@@ -49,48 +99,71 @@ def cpu_baseline(seconds):
     t = time.perf_counter()
     o.step(n)
     dt = time.perf_counter() - t
-    return {"value": cells * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+    return {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{case['name']} (256x512 window of the same seed), {n} steps, float64, one thread"}
+
+
+def batch_forms(torch, Solver, inputs, steps, warmup):
+    """48 uneven bubble cases (16 each of 150x300, 200x400, 300x600): one
+    batched launch per step vs the same cases advanced one by one."""
+    cases = inputs.batch_sweep()
+    cells = sum(c["params"]["nx"] * c["params"]["ny"] for c in cases)
+    b = Solver([c["params"] for c in cases])
+    for k, c in enumerate(cases):
+        b.init_fields(k, c["C"], c["u"], c["p"])
+    bvar = b.autotune(steps=3)
+    ms_b, _ = timed_steps(torch, [b], steps, warmup)
+    singles = []
+    for c in cases:
+        s = Solver(c["params"])
+        s.init_fields(0, c["C"], c["u"], c["p"])
+        s.set_variant(s.variants().index(bvar))
+        singles.append(s)
+    ms_s, _ = timed_steps(torch, singles, steps, warmup)
+    return {"cases": len(cases), "cells": cells, "variant": bvar,
+            "batched_mlups": round(cells / (ms_b * 1e-3) / 1e6, 1),
+            "one_by_one_mlups": round(cells / (ms_s * 1e-3) / 1e6, 1),
+            "batched_ms_per_step": round(ms_b, 4), "one_by_one_ms_per_step": round(ms_s, 4)}
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the method's domain is advanced by "
-              "one device here", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): every workload here is advanced "
+              "by a single device", file=sys.stderr)
         sys.exit(2)
     import torch
+    if a.copy_probe > 0:
+        n = a.copy_probe * (1 << 20)
+        x = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": 5}), flush=True)
+        return
     from paper_2207_09431_amd import inputs
     from paper_2207_09431_amd.pflbm import Solver
 
     case = inputs.many_bubbles(a.nx, a.ny, a.bubbles)
     prm = dict(case["params"])
-    prm["store_h"] = a.store_h
     s = Solver(prm, device="cuda:0")
+    s.init_fields(0, case["C"], case["u"], case["p"])
     if a.variant >= 0:
         s.set_variant(a.variant)
-    s.init_fields(0, case["C"], case["u"], case["p"])
+        variant = s.variants()[a.variant]
+        tuning = None
+    else:
+        variant = s.autotune(steps=5)
+        tuning = {k: round(v, 4) for k, v in s.tuning.items()}
     torch.cuda.synchronize()
     cells = prm["nx"] * prm["ny"]
 
-    s.step(a.warmup)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    stream = s.stream
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    s.step(a.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1) / a.steps
+    ms, wall = timed_steps(torch, [s], a.steps, a.warmup)
     mlups = cells / (ms * 1e-3) / 1e6
-
     diag = s.bubble_centroid_velocity(0, 0)
     bpu = s.bytes_per_update()
     achieved = bpu * cells / (ms * 1e-3) / 1e9
-    variant = s.variants()[s_variant(s, a.variant)]
     out = {
         "metric": "MLUPS (D2Q9 g+h)",
         "value": round(mlups, 1),
@@ -106,21 +179,32 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{case['name']}: {a.nx}x{a.ny} single domain, {a.bubbles} seeded bubbles R 25-40, "
-                        f"power-law liquid n=0.6 K=0.1, density ratio 1000, float32 "
-                        f"{'stored hbar' if a.store_h else 'C_i state (tau_h=1/2)'}",
+                        f"power-law liquid n=0.6 K=0.1, density ratio 1000, float32 arithmetic, "
+                        f"state gbar float32 + C float64 + tau float32 (tau_h = 1/2)",
             "nx": a.nx, "ny": a.ny, "cells": cells, "bytes_per_update": bpu, "kernel_variant": variant,
-            "wall_s_timed": round(wall, 4), "gas_mass": diag[0],
+            "autotune_ms_per_step": tuning, "wall_s_timed": round(wall, 4), "gas_mass": diag[0],
         },
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(variant, a.nx, a.ny)},
     }
+    del s
+    torch.cuda.empty_cache()
+    if not a.no_forms:
+        forms = {"batched_48": batch_forms(torch, Solver, inputs, max(20, a.steps // 4), 5)}
+        torch.cuda.empty_cache()
+        sh = Solver(dict(prm, store_h=1), device="cuda:0")
+        sh.init_fields(0, case["C"], case["u"], case["p"])
+        sh.set_variant(sh.variants().index(variant))
+        ms_h, _ = timed_steps(torch, [sh], max(20, a.steps // 4), 5)
+        forms["stored_hbar"] = {"mlups": round(cells / (ms_h * 1e-3) / 1e6, 1), "ms_per_step": round(ms_h, 4),
+                                "bytes_per_update": sh.bytes_per_update(),
+                                "achieved_GBs": round(sh.bytes_per_update() * cells / (ms_h * 1e-3) / 1e9, 1)}
+        del sh
+        out["forms"] = forms
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)
-
-
-def s_variant(s, requested):
-    return requested if requested >= 0 else 0
 
 
 if __name__ == "__main__":
