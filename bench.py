@@ -6,7 +6,8 @@ arithmetic.  A "step" is one time step of the whole domain (collision,
 streaming, bounce-back, phase-field update); the timed region covers exactly
 `--steps` steps with the state resident in HBM.  The tile variant is chosen by
 the autotuner before timing.  Prints one JSON line; the "forms" object adds
-the batched 48-case sweep (batched vs one by one) and the stored-hbar form.
+the batched 48-case sweep (batched vs one by one), the stored-hbar form and
+the float16 storage form.
 """
 import argparse
 import json
@@ -201,6 +202,15 @@ def main():
                                 "bytes_per_update": sh.bytes_per_update(),
                                 "achieved_GBs": round(sh.bytes_per_update() * cells / (ms_h * 1e-3) / 1e9, 1)}
         del sh
+        torch.cuda.empty_cache()
+        sq = Solver(dict(prm, storage=1), device="cuda:0")
+        sq.init_fields(0, case["C"], case["u"], case["p"])
+        qvar = sq.autotune(steps=5)
+        ms_q, _ = timed_steps(torch, [sq], max(20, a.steps // 4), 5)
+        forms["float16_storage"] = {"mlups": round(cells / (ms_q * 1e-3) / 1e6, 1), "ms_per_step": round(ms_q, 4),
+                                    "variant": qvar, "bytes_per_update": sq.bytes_per_update(),
+                                    "achieved_GBs": round(sq.bytes_per_update() * cells / (ms_q * 1e-3) / 1e9, 1)}
+        del sq
         out["forms"] = forms
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)

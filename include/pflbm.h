@@ -66,9 +66,25 @@ typedef struct {
     double tau_h;              /* relaxation time of hbar (0.5 in the paper) */
     double g;                  /* gravity: F_b = rho (fx, -g) (Eq. (12)) */
     double fx;                 /* horizontal body acceleration (0 in the paper's bubble runs) */
-    int32_t storage;           /* 0: float32 populations, 1: float16 deviations (see below) */
+    int32_t storage;           /* 0: gbar deviations in float32; 1: in float16 (see below) */
     int32_t store_h;           /* 0: keep only C_i when tau_h = 0.5 (exact), 1: store hbar */
 } pflbm_params;
+
+/*
+ * State forms.  gbar is kept as s = sum_a gbar_a (float32) and the deviations
+ * from the rest-state weights d_a = gbar_a - w_a s, a = 1..8 (d_0 follows
+ * from sum_a d_a = 0); C_i is kept in float64 and tau in float32.
+ *  - storage = 0: d_a in float32 (96 B moved per lattice update, two-phase).
+ *  - storage = 1: s and the momentum j = sum_a e_a d_a in float32, and the
+ *    six pair moments (d1+d3, d2+d4, d5+d7, d6+d8, d5-d7, d6-d8) * 2^14
+ *    rounded to float16 (nearest even): 72 B per update; the arithmetic
+ *    stays float32.  Float16 rounding then reaches only moments that the
+ *    collision relaxes.  Requires store_h = 0.
+ *  - store_h = 0 (requires tau_h = 0.5): hbar relaxes at rate 1, so the
+ *    post-collision hbar depends only on time-t fields and keeping C_i alone
+ *    is exact.  store_h = 1 keeps the 9 n_h hbar planes (float32), for any
+ *    tau_h.
+ */
 
 /*
  * Workspace bytes for the given cases (device memory, 256-byte aligned base).
@@ -84,9 +100,9 @@ size_t pflbm_workspace_bytes(const pflbm_params* cases, int32_t ncases);
  * hipStream_t or NULL.  Errors: INVALID_ARG for out-of-range parameters
  * (nx or ny < 5, n_h not 1 or 2, rho_k <= 0, nu_k <= 0, nu_min <= 0 or
  * nu_min > nu_max, K <= 0 with a power-law component, xi <= 0, D0 < 0,
- * tau_h <= 0, a Sigma_i <= 0, store_h = 0 with tau_h != 0.5);
- * WORKSPACE when the workspace is NULL, small or misaligned; DEVICE when a
- * HIP call fails.
+ * tau_h <= 0, a Sigma_i <= 0, store_h = 0 with tau_h != 0.5, storage not
+ * 0 or 1); UNSUPPORTED for storage = 1 with store_h = 1; WORKSPACE when the
+ * workspace is NULL, small or misaligned; DEVICE when a HIP call fails.
  */
 int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspace, size_t bytes,
                      void* hip_stream, pflbm_ctx** out);

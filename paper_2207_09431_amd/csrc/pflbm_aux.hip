@@ -33,7 +33,7 @@ __device__ __forceinline__ NodeStencil stencil_at(const CaseDev& cd, int x, int 
     const float c1 = (float)d1, c2 = (float)d2;
     n.c[0] = c1;
     n.c[1] = c2;
-    n.rho = mix_rho(cd, c1, c2);
+    n.rho = mix_rho(cd, d1, d2);
     float sx[2] = {0.f, 0.f}, sy[2] = {0.f, 0.f}, sl[2] = {0.f, 0.f}, rx = 0.f, ry = 0.f;
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
@@ -48,7 +48,7 @@ __device__ __forceinline__ NodeStencil stencil_at(const CaseDev& cd, int x, int 
         sx[1] += w * Lat::ex[a] * (p2 - m2);
         sy[1] += w * Lat::ey[a] * (p2 - m2);
         sl[1] += w * ((p2 - c2) + (m2 - c2));
-        const float dr = mix_rho(cd, p1, p2) - mix_rho(cd, m1, m2);
+        const float dr = mix_rho(cd, q1, q2) - mix_rho(cd, r1, r2);
         rx += w * Lat::ex[a] * dr;
         ry += w * Lat::ey[a] * dr;
     }
@@ -70,11 +70,9 @@ __device__ __forceinline__ void node_macro(const CaseDev& cd, int par, int x, in
     const double* C = cd.C[par];
     n = stencil_at(cd, x, y, [&](int xx, int yy, double& a, double& b) { load_c(cd, C, xx, yy, a, b); });
     const long long off = (long long)y * cd.pitch + x;
-    const float* S = cd.S[par];
     float d[9];
-#pragma unroll
-    for (int a = 1; a < 9; ++a) d[a] = S[a * cd.plane + off];
-    const float s = S[off];
+    load_devs(cd, par, off, d);
+    const float s = cd.S[par][off];
     const float jx = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
     const float jy = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
     const float mu13 = n.mu[0] - n.mu[2], mu23 = n.mu[1] - n.mu[2];
@@ -130,13 +128,15 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const CaseDev* __restrict_
         const float eu = Lat::ex[a] * ux + Lat::ey[a] * uy;
         A[a] = 3.0f * eu + 4.5f * eu * eu - 1.5f * uu;
     }
+    float dq[9];
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
         const float wa = Lat::w[a];
         const float egr = Lat::ex[a] * st.grx + Lat::ey[a] * st.gry - ugr;
         const float eF = Lat::ex[a] * Fx + Lat::ey[a] * Fy - uF;
-        S[a * cd.plane + off] = wa * ps + rc2 * wa * A[a] - 0.5f * (kCs2 * egr * wa * A[a] + eF * wa * (1.0f + A[a]));
+        dq[a] = wa * ps + rc2 * wa * A[a] - 0.5f * (kCs2 * egr * wa * A[a] + eF * wa * (1.0f + A[a]));
     }
+    store_devs(cd, par, off, dq);
     double* C = cd.C[par];
     for (int i = 0; i < cd.n_h; ++i) C[i * cd.plane + off] = Cin[(long long)i * n + q];
     if (cd.H[par]) {
@@ -181,11 +181,11 @@ __global__ __launch_bounds__(kBlock) void export_kernel(const CaseDev* __restric
     if (q >= (long long)nx * ny) return;
     const int y = (int)(q / nx), x = (int)(q - (long long)y * nx);
     const long long n = (long long)nx * ny, off = (long long)y * cd.pitch + x;
-    const float* S = cd.S[par];
-    const float s = S[off];
-    float d0 = 0.f;
+    const float s = cd.S[par][off];
+    float d0 = 0.f, dd[9];
+    load_devs(cd, par, off, dd);
     for (int a = 1; a < 9; ++a) {
-        const float da = S[a * cd.plane + off];
+        const float da = dd[a];
         d0 -= da;
         out[a * n + q] = Lat::w[a] * s + da;
     }

@@ -23,7 +23,8 @@ constexpr float kCs2 = 1.0f / 3.0f;
 // Per-case block in device memory.  State planes are row-major (ny, pitch);
 // `plane` is the element stride between planes.  The gbar state is kept as
 // s = sum_a gbar_a in plane 0 and the deviations d_a = gbar_a - w_a s
-// (a = 1..8) in planes 1..8 (float32); d_0 = -sum_{a>0} d_a.  The phase
+// (a = 1..8) in planes 1..8 (float32; the float16 form is described below);
+// d_0 = -sum_{a>0} d_a.  The phase
 // fields C_i are accumulated in float64 planes: their per-step change is far
 // below the float32 spacing near C = 1, and rounding it into a float32 state
 // drifts the component mass.
@@ -34,6 +35,10 @@ struct CaseDev {
     double* C[2];       // n_h planes each (float64)
     float* T[2];        // tau of the previous step
     float* H[2];        // 9*n_h planes each when hbar is stored, else null
+    // float16 storage form: S holds s, j_x, j_y (float32) and Q the six pair
+    // moments of the deviations (float16, scaled by qscale); null otherwise
+    _Float16* Q[2];
+    float qscale, qinv;
     float rho[3], nu[3];
     int plc;            // power-law component or -1
     int vm;             // variable mobility
@@ -46,6 +51,7 @@ struct CaseDev {
     float g, fx;
     // float64 coefficients of the bulk chemical potential; dA_j = 4 Sigma_T / (xi Sigma_j)
     double dsig12, dsig13, dsig23, dlam, dSig[3], dA[3];
+    double drho[3];     // component densities in float64
 };
 
 struct TileDev {
@@ -68,9 +74,72 @@ __device__ __forceinline__ int mirror_y(int y, int ny) {
     return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
 }
 
-// Mixture density with concentrations limited to [0, 1].
-__device__ __forceinline__ float mix_rho(const CaseDev& cd, float c1, float c2) {
-    return cd.rho[0] * clip01(c1) + cd.rho[1] * clip01(c2) + cd.rho[2] * clip01(1.0f - c1 - c2);
+// Float16 storage form.  The momentum j = sum_a e_a d_a stays float32 (it is
+// conserved by the collision, so rounding it would persist, and at density
+// ratio 1000 it is a small difference of the deviations); the rest of the
+// deviations is kept as six pair moments in float16,
+//   m = (d1+d3, d2+d4, d5+d7, d6+d8, d5-d7, d6-d8),
+// whose rounding only reaches non-conserved moments, which the collision
+// relaxes.  Scale 2^14: |m| up to 4 stays finite, values down to 4e-9 stay
+// normal, and the scaling is exact.
+constexpr float kQScale = 16384.0f;
+constexpr int kQPlanes = 6;    // float16 planes
+constexpr int kSPlanes16 = 3;  // float32 planes: s, j_x, j_y
+
+__device__ __forceinline__ void pack_devs(const float d[9], float& jx, float& jy, float m[6]) {
+    const float x5 = d[5] - d[7], x6 = d[6] - d[8];
+    jx = (d[1] - d[3]) + (x5 - x6);
+    jy = (d[2] - d[4]) + (x5 + x6);
+    m[0] = d[1] + d[3];
+    m[1] = d[2] + d[4];
+    m[2] = d[5] + d[7];
+    m[3] = d[6] + d[8];
+    m[4] = x5;
+    m[5] = x6;
+}
+__device__ __forceinline__ void unpack_devs(float jx, float jy, const float m[6], float d[9]) {
+    const float x1 = jx - (m[4] - m[5]), y1 = jy - (m[4] + m[5]);
+    d[1] = 0.5f * (m[0] + x1);
+    d[3] = 0.5f * (m[0] - x1);
+    d[2] = 0.5f * (m[1] + y1);
+    d[4] = 0.5f * (m[1] - y1);
+    d[5] = 0.5f * (m[2] + m[4]);
+    d[7] = 0.5f * (m[2] - m[4]);
+    d[6] = 0.5f * (m[3] + m[5]);
+    d[8] = 0.5f * (m[3] - m[5]);
+}
+
+// Deviations d_1..d_8 of buffer `par` at element offset `off`, in either
+// storage form (used by the once-per-call kernels).
+__device__ __forceinline__ void load_devs(const CaseDev& cd, int par, long long off, float d[9]) {
+    if (cd.Q[par]) {
+        float m[6];
+        for (int k = 0; k < kQPlanes; ++k) m[k] = (float)cd.Q[par][k * cd.plane + off] * cd.qinv;
+        unpack_devs(cd.S[par][cd.plane + off], cd.S[par][2 * cd.plane + off], m, d);
+    } else {
+        for (int a = 1; a < 9; ++a) d[a] = cd.S[par][a * cd.plane + off];
+    }
+}
+__device__ __forceinline__ void store_devs(const CaseDev& cd, int par, long long off, const float d[9]) {
+    if (cd.Q[par]) {
+        float jx, jy, m[6];
+        pack_devs(d, jx, jy, m);
+        cd.S[par][cd.plane + off] = jx;
+        cd.S[par][2 * cd.plane + off] = jy;
+        for (int k = 0; k < kQPlanes; ++k) cd.Q[par][k * cd.plane + off] = (_Float16)(m[k] * cd.qscale);
+    } else {
+        for (int a = 1; a < 9; ++a) cd.S[par][a * cd.plane + off] = d[a];
+    }
+}
+
+// Mixture density with concentrations limited to [0, 1], formed in float64
+// from the float64 phase fields: inside a bubble C_1 = 1 - O(1e-5), and
+// 1 - C_1 in float32 would carry a relative error of O(1e-3) into a liquid
+// term that is a few percent of the gas density.
+__device__ __forceinline__ float mix_rho(const CaseDev& cd, double c1, double c2) {
+    const double a = fmin(fmax(c1, 0.0), 1.0), b = fmin(fmax(c2, 0.0), 1.0);
+    const double c = fmin(fmax(1.0 - c1 - c2, 0.0), 1.0);
+    return (float)(cd.drho[0] * a + cd.drho[1] * b + cd.drho[2] * c);
 }
 
 // Hardware reciprocal (1 ulp), instead of the correctly rounded division

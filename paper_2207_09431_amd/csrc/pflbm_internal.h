@@ -9,7 +9,9 @@ namespace pflbm {
 // fused step kernel variants (pflbm_step.hip)
 int step_variant_count();
 bool step_variant_shape(int v, int nh, int* tx, int* ty, int* nt);
-hipError_t launch_step(int v, int nh, bool sh, const CaseDev* cases, const TileDev* tiles, int ntiles, int par,
+// state forms of the step: compact float32, stored hbar float32, compact float16
+constexpr int kStepForms = 3;
+hipError_t launch_step(int v, int nh, int form, const CaseDev* cases, const TileDev* tiles, int ntiles, int par,
                        hipStream_t stream);
 
 // auxiliary kernels (pflbm_aux.hip); `cd_dev` points to the case block in

@@ -23,7 +23,7 @@ constexpr int kReduceMax = 1024;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct CaseLayout {
-    size_t S[2], C[2], T[2], H[2];   // byte offsets into the workspace
+    size_t S[2], C[2], T[2], H[2], Q[2];   // byte offsets into the workspace
     int pitch;
     long long plane;                 // elements per plane
 };
@@ -125,8 +125,11 @@ bool make_layout(const pflbm_params* cases, int n, Layout* L) {
         cl.pitch = (int)align_up((size_t)p.nx, kPitchElems);
         cl.plane = (long long)cl.pitch * p.ny;
         const size_t pb = sizeof(float) * (size_t)cl.plane;
+        const bool f16 = p.storage == 1;
         for (int b = 0; b < 2; ++b) {
-            cl.S[b] = off; off = align_up(off + 9 * pb, kAlign);
+            cl.S[b] = off; off = align_up(off + (f16 ? kSPlanes16 : 9) * pb, kAlign);
+            if (f16) { cl.Q[b] = off; off = align_up(off + kQPlanes * (pb / 2), kAlign); }
+            else cl.Q[b] = 0;
             cl.C[b] = off; off = align_up(off + (size_t)p.n_h * 2 * pb, kAlign);   // float64
             cl.T[b] = off; off = align_up(off + pb, kAlign);
             if (p.store_h) { cl.H[b] = off; off = align_up(off + 9 * (size_t)p.n_h * pb, kAlign); }
@@ -208,7 +211,7 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
     *out = nullptr;
     Layout L;
     if (!cases || ncases <= 0 || !make_layout(cases, ncases, &L)) return PFLBM_ERR_INVALID_ARG;
-    if (cases[0].storage != 0) return PFLBM_ERR_UNSUPPORTED;
+    if (cases[0].storage == 1 && cases[0].store_h) return PFLBM_ERR_UNSUPPORTED;
     if (!d_workspace || bytes < L.total || ((uintptr_t)d_workspace % kAlign) != 0) return PFLBM_ERR_WORKSPACE;
     pflbm_ctx* c = new (std::nothrow) pflbm_ctx;
     if (!c) return PFLBM_ERR_DEVICE;
@@ -231,8 +234,11 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
             d.C[b] = reinterpret_cast<double*>(c->ws + cl.C[b]);
             d.T[b] = reinterpret_cast<float*>(c->ws + cl.T[b]);
             d.H[b] = p.store_h ? reinterpret_cast<float*>(c->ws + cl.H[b]) : nullptr;
+            d.Q[b] = p.storage == 1 ? reinterpret_cast<_Float16*>(c->ws + cl.Q[b]) : nullptr;
         }
-        for (int j = 0; j < 3; ++j) { d.rho[j] = (float)p.rho[j]; d.nu[j] = (float)p.nu[j]; }
+        d.qscale = kQScale;
+        d.qinv = 1.0f / kQScale;
+        for (int j = 0; j < 3; ++j) { d.rho[j] = (float)p.rho[j]; d.drho[j] = p.rho[j]; d.nu[j] = (float)p.nu[j]; }
         d.plc = p.powerlaw_comp;
         d.vm = p.variable_mobility ? 1 : 0;
         d.K = (float)p.K; d.nexp = (float)p.n; d.numin = (float)p.nu_min; d.numax = (float)p.nu_max;
@@ -283,7 +289,8 @@ int32_t pflbm_init_fields(pflbm_ctx* c, int32_t k, const double* C, const double
 static hipError_t launch_one(pflbm_ctx* c, int par) {
     const CaseDev* cases = dev_case(c, 0);
     const TileDev* tiles = reinterpret_cast<const TileDev*>(c->ws + c->L.tiles_off);
-    return launch_step(c->variant, c->prm[0].n_h, c->prm[0].store_h != 0, cases, tiles, c->ntiles, par, c->stream);
+    const int form = c->prm[0].storage == 1 ? 2 : (c->prm[0].store_h ? 1 : 0);
+    return launch_step(c->variant, c->prm[0].n_h, form, cases, tiles, c->ntiles, par, c->stream);
 }
 
 static void drop_graph(pflbm_ctx* c) {
@@ -473,8 +480,10 @@ void* pflbm_stream(const pflbm_ctx* c) { return c ? (void*)c->stream : nullptr; 
 double pflbm_bytes_per_update(const pflbm_ctx* c) {
     if (!c) return 0.0;
     const pflbm_params& p = c->prm[0];
-    double b = 9 * 4 + 8.0 * p.n_h + 4;    // gbar (s + 8 deviations, float32), C_i (float64), tau
-    if (p.store_h) b += 9 * 4.0 * p.n_h;   // hbar
+    // gbar: s + 8 deviations (float32), or s, j_x, j_y (float32) + 6 pair
+    // moments (float16); C_i (float64); tau (float32); hbar (float32) when stored
+    double b = (p.storage == 1 ? 3 * 4 + 6 * 2 : 9 * 4) + 8.0 * p.n_h + 4;
+    if (p.store_h) b += 9 * 4.0 * p.n_h;
     return 2.0 * b;                        // read once and written once
 }
 

@@ -66,7 +66,7 @@ __device__ __forceinline__ void md_all(const float* f, int i, float d[9], float&
     gy = (1.0f / 3.0f) * (d[2] - d[4]) + (1.0f / 12.0f) * (p5 + p6);
 }
 
-template <int TX, int TY, int NH, bool SH, int NT>
+template <int TX, int TY, int NH, bool SH, bool F16, int NT>
 __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ cases,
                                                   const TileDev* __restrict__ tiles, int ntiles, int par) {
     constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
@@ -106,6 +106,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     const auto Tout = gmem<float>(cd.T[par ^ 1]);
     const auto Hin = gmem<const float>(cd.H[par]);
     const auto Hout = gmem<float>(cd.H[par ^ 1]);
+    const auto Qin = gmem<const _Float16>(cd.Q[par]);
+    const auto Qout = gmem<_Float16>(cd.Q[par ^ 1]);
+    const float qinv = cd.qinv, qscale = cd.qscale;
     const int tid = threadIdx.x;
 
     // ---------------- phase A: C_i and rho on R3
@@ -119,7 +122,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         sC[0][idx] = c1;
         sCd[0][idx] = d1;
         if (NH == 2) { sC[NH - 1][idx] = c2; sCd[NH - 1][idx] = d2; }
-        sR[idx] = mix_rho(cd, c1, c2);
+        sR[idx] = mix_rho(cd, d1, d2);
     }
     __syncthreads();
 
@@ -142,12 +145,18 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         if (gyr >= 0 && gyr < ny) {
             const int gx = wrap_x(x0 - 2 + rx, nx);
             const long long off = (long long)gyr * pitch + gx;
-            float d[9];
-#pragma unroll
-            for (int a = 1; a < 9; ++a) d[a] = Sin[a * plane + off];
             const float s = Sin[off];
-            const float jx = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
-            const float jy = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
+            float jx, jy;
+            if (F16) {
+                jx = Sin[plane + off];
+                jy = Sin[2 * plane + off];
+            } else {
+                float d[9];
+#pragma unroll
+                for (int a = 1; a < 9; ++a) d[a] = Sin[a * plane + off];
+                jx = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
+                jy = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
+            }
             float grx, gry;
             cd_grad<W3>(sR, i3, grx, gry);
             const float rho = sR[i3];
@@ -192,8 +201,15 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const long long off = (long long)gyr * pitch + gx;
 
         float d[9];
+        if (F16) {
+            float m[kQPlanes];
 #pragma unroll
-        for (int a = 1; a < 9; ++a) d[a] = Sin[a * plane + off];
+            for (int k = 0; k < kQPlanes; ++k) m[k] = (float)Qin[k * plane + off] * qinv;
+            unpack_devs(Sin[plane + off], Sin[2 * plane + off], m, d);
+        } else {
+#pragma unroll
+            for (int a = 1; a < 9; ++a) d[a] = Sin[a * plane + off];
+        }
         const float s = Sin[off];
         d[0] = -(d[1] + d[2] + d[3] + d[4] + d[5] + d[6] + d[7] + d[8]);
         const float tprev = Tin[off];
@@ -371,8 +387,19 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         }
         const float snew = sy0 + (ssum + dsum);
         Sout[off] = snew;
+        if (F16) {
+            float da[9], jx, jy, m[kQPlanes];
 #pragma unroll
-        for (int a = 1; a < 9; ++a) Sout[a * plane + off] = Lat::w[a] * (sv[a] - snew) + dv[a];
+            for (int a = 1; a < 9; ++a) da[a] = Lat::w[a] * (sv[a] - snew) + dv[a];
+            pack_devs(da, jx, jy, m);
+            Sout[plane + off] = jx;
+            Sout[2 * plane + off] = jy;
+#pragma unroll
+            for (int k = 0; k < kQPlanes; ++k) Qout[k * plane + off] = (_Float16)(m[k] * qscale);   // nearest even
+        } else {
+#pragma unroll
+            for (int a = 1; a < 9; ++a) Sout[a * plane + off] = Lat::w[a] * (sv[a] - snew) + dv[a];
+        }
 
         // region index of the output node and of each source on R3 (for C)
         const int j3 = (oy + 3) * W3 + ox + 3;
@@ -413,20 +440,20 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
 }
 
 // Step variants selectable at run time: tile shape x phase-field count x
-// hbar storage.  A tile shape whose LDS footprint exceeds the 160 KiB of a
-// gfx950 CU for two phase fields is offered for one phase field only.
+// state form (compact float32, stored hbar float32, compact float16).  A tile
+// shape whose LDS footprint exceeds the 160 KiB of a gfx950 CU for two phase
+// fields is offered for one phase field only.
+using StepFn = void (*)(const CaseDev*, const TileDev*, int, int);
 struct StepVariant {
     int tx, ty, nt;
-    void (*k1[2])(const CaseDev*, const TileDev*, int, int);   // n_h = 1: compact, stored hbar
-    void (*k2[2])(const CaseDev*, const TileDev*, int, int);   // n_h = 2
+    StepFn k[2][kStepForms];   // [n_h - 1][form]
 };
 
-#define PFLBM_K(TX, TY, NH, SH, NT) step_kernel<TX, TY, NH, SH, NT>
-#define PFLBM_V2(TX, TY, NT)                                                                        \
-    {TX, TY, NT, {PFLBM_K(TX, TY, 1, false, NT), PFLBM_K(TX, TY, 1, true, NT)},                      \
-     {PFLBM_K(TX, TY, 2, false, NT), PFLBM_K(TX, TY, 2, true, NT)}}
-#define PFLBM_V1(TX, TY, NT)                                                                        \
-    {TX, TY, NT, {PFLBM_K(TX, TY, 1, false, NT), PFLBM_K(TX, TY, 1, true, NT)}, {nullptr, nullptr}}
+#define PFLBM_K(TX, TY, NH, SH, F16, NT) step_kernel<TX, TY, NH, SH, F16, NT>
+#define PFLBM_FORMS(TX, TY, NH, NT) \
+    {PFLBM_K(TX, TY, NH, false, false, NT), PFLBM_K(TX, TY, NH, true, false, NT), PFLBM_K(TX, TY, NH, false, true, NT)}
+#define PFLBM_V2(TX, TY, NT) {TX, TY, NT, {PFLBM_FORMS(TX, TY, 1, NT), PFLBM_FORMS(TX, TY, 2, NT)}}
+#define PFLBM_V1(TX, TY, NT) {TX, TY, NT, {PFLBM_FORMS(TX, TY, 1, NT), {nullptr, nullptr, nullptr}}}
 
 static const StepVariant kVariants[] = {
     PFLBM_V2(32, 16, 512),
@@ -442,20 +469,21 @@ int step_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])
 bool step_variant_shape(int v, int nh, int* tx, int* ty, int* nt) {
     if (v < 0 || v >= step_variant_count() || (nh != 1 && nh != 2)) return false;
     const StepVariant& sv = kVariants[v];
-    if ((nh == 1 ? sv.k1[0] : sv.k2[0]) == nullptr) return false;
+    if (sv.k[nh - 1][0] == nullptr) return false;
     *tx = sv.tx;
     *ty = sv.ty;
     *nt = sv.nt;
     return true;
 }
 
-hipError_t launch_step(int v, int nh, bool sh, const CaseDev* cases, const TileDev* tiles, int ntiles, int par,
+hipError_t launch_step(int v, int nh, int form, const CaseDev* cases, const TileDev* tiles, int ntiles, int par,
                        hipStream_t stream) {
-    if (v < 0 || v >= step_variant_count() || (nh != 1 && nh != 2) || ntiles <= 0) return hipErrorInvalidValue;
-    const StepVariant& sv = kVariants[v];
-    auto k = (nh == 1 ? sv.k1 : sv.k2)[sh ? 1 : 0];
+    if (v < 0 || v >= step_variant_count() || (nh != 1 && nh != 2) || form < 0 || form >= kStepForms ||
+        ntiles <= 0)
+        return hipErrorInvalidValue;
+    const StepFn k = kVariants[v].k[nh - 1][form];
     if (!k) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k, dim3(ntiles), dim3(sv.nt), 0, stream, cases, tiles, ntiles, par);
+    hipLaunchKernelGGL(k, dim3(ntiles), dim3(kVariants[v].nt), 0, stream, cases, tiles, ntiles, par);
     return hipGetLastError();
 }
 

@@ -44,6 +44,18 @@ def test_workspace_bytes_valid_and_invalid(L):
     # batched cases must agree on n_h / storage / store_h
     assert pflbm.workspace_bytes([prm, dict(prm, n_h=2)]) == 0
     assert pflbm.workspace_bytes([prm, dict(prm, nx=80, ny=90)]) > n
+    assert pflbm.workspace_bytes([prm, dict(prm, storage=1)]) == 0
+    assert pflbm.workspace_bytes([dict(prm, storage=2)]) == 0
+
+
+def test_float16_form_is_smaller(L):
+    prm = inputs.many_bubbles_crop()["params"]
+    n32 = pflbm.workspace_bytes([prm])
+    n16 = pflbm.workspace_bytes([dict(prm, storage=1)])
+    plane = 256 * 512
+    # per ping-pong buffer: 8 float32 deviation planes become 2 float32
+    # momentum planes + 6 float16 pair-moment planes
+    assert n32 - n16 == 2 * (8 * 4 - 2 * 4 - 6 * 2) * plane
 
 
 def test_status_strings(L):
