@@ -66,6 +66,13 @@ __device__ __forceinline__ int wrap_x(int x, int nx) {
     while (x >= nx) x -= nx;
     return x;
 }
+// Branch-free wrap for tile regions: exact for x in [-nx, 2 nx); larger x
+// (halo nodes of a ragged last tile more than nx beyond the edge, whose
+// values never reach an output) are clamped to a valid column.
+__device__ __forceinline__ int wrap_x_tile(int x, int nx) {
+    x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+    return x < nx ? x : nx - 1;
+}
 // Mirror about the walls at y = -1/2 and y = ny - 1/2 (zero normal
 // derivative of the stencil fields); rows farther than ny away are clamped.
 __device__ __forceinline__ int mirror_y(int y, int ny) {

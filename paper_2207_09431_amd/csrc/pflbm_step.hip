@@ -112,22 +112,63 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     const int tid = threadIdx.x;
 
     // ---------------- phase A: C_i and rho on R3
-    for (int idx = tid; idx < N3; idx += NT) {
+    // All global loads of phases A and B are issued here, phase A's first, so
+    // that the latency of the gbar loads (consumed in phase B) overlaps
+    // phase A.  Each thread owns the nodes idx = tid + k NT of each region.
+    // The loads are unconditional (surplus threads and rows beyond the walls
+    // read a valid node and discard it) so that no branch forces an early wait.
+    constexpr int KA = (N3 + NT - 1) / NT, KB = (N2 + NT - 1) / NT;
+    double ca[KA][NH];
+#pragma unroll
+    for (int k = 0; k < KA; ++k) {
+        const int idx = min(tid + k * NT, N3 - 1);
         const int ry = idx / W3, rx = idx - ry * W3;
-        const int gx = wrap_x(x0 - 3 + rx, nx), gy = mirror_y(y0 - 3 + ry, ny);
+        const int gx = wrap_x_tile(x0 - 3 + rx, nx), gy = mirror_y(y0 - 3 + ry, ny);
         const long long off = (long long)gy * pitch + gx;
-        const double d1 = Cin[off];
-        const double d2 = NH == 2 ? Cin[plane + off] : 0.0;
-        const float c1 = (float)d1, c2 = (float)d2;
-        sC[0][idx] = c1;
+#pragma unroll
+        for (int i = 0; i < NH; ++i) ca[k][i] = Cin[i * plane + off];
+    }
+    // gbar state of the R2 nodes: s, the momentum and (used for the R1 nodes)
+    // the rest of the deviations and tau
+    constexpr int ND = F16 ? 2 + kQPlanes : 8;
+    float ps[KB], pd[KB][ND], pt[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int idx = min(tid + k * NT, N2 - 1);
+        const int ry = idx / W2, rx = idx - ry * W2;
+        const long long off = (long long)mirror_y(y0 - 2 + ry, ny) * pitch + wrap_x_tile(x0 - 2 + rx, nx);
+        ps[k] = Sin[off];
+        if (F16) {
+            pd[k][0] = Sin[plane + off];
+            pd[k][1] = Sin[2 * plane + off];
+#pragma unroll
+            for (int q = 0; q < kQPlanes; ++q) pd[k][2 + q] = (float)Qin[q * plane + off];
+        } else {
+#pragma unroll
+            for (int a = 1; a < 9; ++a) pd[k][a - 1] = Sin[a * plane + off];
+        }
+        pt[k] = Tin[off];
+    }
+    // surplus threads (idx >= N3) repeat node N3 - 1: same address, same value
+#pragma unroll
+    for (int k = 0; k < KA; ++k) {
+        const int idx = min(tid + k * NT, N3 - 1);
+        const double d1 = ca[k][0];
+        const double d2 = NH == 2 ? ca[k][NH - 1] : 0.0;
+        sC[0][idx] = (float)d1;
         sCd[0][idx] = d1;
-        if (NH == 2) { sC[NH - 1][idx] = c2; sCd[NH - 1][idx] = d2; }
+        if (NH == 2) { sC[NH - 1][idx] = (float)d2; sCd[NH - 1][idx] = d2; }
         sR[idx] = mix_rho(cd, d1, d2);
     }
     __syncthreads();
 
-    // ---------------- phase B: mu, u, p on R2
-    for (int idx = tid; idx < N2; idx += NT) {
+    // ---------------- phase B: mu, u, p on R2; the gbar state and tau of the
+    // R1 nodes are parked in sD, sS and sDif, which phase C reads and then
+    // overwrites node by node
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int idx = tid + k * NT;
+        if (idx >= N2) continue;
         const int ry = idx / W2, rx = idx - ry * W2;
         const int i3 = (ry + 1) * W3 + rx + 1;
         const int gyr = y0 - 2 + ry;
@@ -143,19 +184,30 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         if (NH == 2) sMu[1][idx] = mu[1];
         sMu[NH][idx] = mu[2];
         if (gyr >= 0 && gyr < ny) {
-            const int gx = wrap_x(x0 - 2 + rx, nx);
-            const long long off = (long long)gyr * pitch + gx;
-            const float s = Sin[off];
+            const float s = ps[k];
             float jx, jy;
+            float d[9];
             if (F16) {
-                jx = Sin[plane + off];
-                jy = Sin[2 * plane + off];
+                jx = pd[k][0];
+                jy = pd[k][1];
             } else {
-                float d[9];
 #pragma unroll
-                for (int a = 1; a < 9; ++a) d[a] = Sin[a * plane + off];
+                for (int a = 1; a < 9; ++a) d[a] = pd[k][a - 1];
                 jx = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
                 jy = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
+            }
+            if (rx >= 1 && rx <= W2 - 2 && ry >= 1 && ry <= H2 - 2) {
+                const int i1 = (ry - 1) * W1 + rx - 1;
+                if (F16) {
+                    float m[kQPlanes];
+#pragma unroll
+                    for (int q = 0; q < kQPlanes; ++q) m[q] = pd[k][2 + q] * qinv;
+                    unpack_devs(jx, jy, m, d);
+                }
+#pragma unroll
+                for (int a = 1; a < 9; ++a) sD[a][i1] = d[a];
+                sS[i1] = s;
+                sDif[0][i1] = pt[k];
             }
             float grx, gry;
             cd_grad<W3>(sR, i3, grx, gry);
@@ -197,22 +249,15 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         if (gyr < 0 || gyr >= ny) continue;   // nodes beyond the walls are never sources
         const int i2 = (ry + 1) * W2 + rx + 1;
         const int i3 = (ry + 2) * W3 + rx + 2;
-        const int gx = wrap_x(x0 - 1 + rx, nx);
+        const int gx = wrap_x_tile(x0 - 1 + rx, nx);
         const long long off = (long long)gyr * pitch + gx;
 
         float d[9];
-        if (F16) {
-            float m[kQPlanes];
 #pragma unroll
-            for (int k = 0; k < kQPlanes; ++k) m[k] = (float)Qin[k * plane + off] * qinv;
-            unpack_devs(Sin[plane + off], Sin[2 * plane + off], m, d);
-        } else {
-#pragma unroll
-            for (int a = 1; a < 9; ++a) d[a] = Sin[a * plane + off];
-        }
-        const float s = Sin[off];
+        for (int a = 1; a < 9; ++a) d[a] = sD[a][idx];
+        const float s = sS[idx];
         d[0] = -(d[1] + d[2] + d[3] + d[4] + d[5] + d[6] + d[7] + d[8]);
-        const float tprev = Tin[off];
+        const float tprev = sDif[0][idx];
 
         // central gradients of C_i and rho, moments and potentials of the node
         float c[2] = {0.f, 0.f}, gcx[2] = {0.f, 0.f}, gcy[2] = {0.f, 0.f};
@@ -323,7 +368,6 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             if (NH == 2) t2 += mu23 * (dc[1][a] - um2);
             sD[a][idx] = d[a] - om * ne[a] + (t1 + t2 * G[a]);
         }
-        sS[idx] = s;
 
         // hbar collision: equilibrium with central differences, forcing with the
         // mixed derivative of C_i and central grad p, source half of Dif
