@@ -55,11 +55,12 @@ __device__ __forceinline__ float edot(int ex, int ey, float vx, float vy) {
 template <int W>
 __device__ __forceinline__ void md_all(const float* f, int i, float d[9], float& gx, float& gy) {
     d[0] = 0.0f;
-    const float fc = f[i];
+    const float fc = -0.75f * f[i];
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
         const int o = Lat::ey[a] * W + Lat::ex[a];
-        d[a] = 0.25f * (-f[i + 2 * o] + 5.0f * f[i + o] - 3.0f * fc - f[i - o]);
+        // [-f(x+2e) + 5 f(x+e) - 3 f(x) - f(x-e)] / 4
+        d[a] = fmaf(0.25f, fmaf(5.0f, f[i + o], -f[i + 2 * o]) - f[i - o], fc);
     }
     const float p5 = d[5] - d[7], p6 = d[6] - d[8];
     gx = (1.0f / 3.0f) * (d[1] - d[3]) + (1.0f / 12.0f) * (p5 - p6);
@@ -306,7 +307,12 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             for (int a = 0; a < 9; ++a) dc[1][a] = 0.0f;
         }
 
-        // force, equilibria (deviation form) and the non-equilibrium second moment
+        // force, equilibrium and the non-equilibrium part.  With
+        // A_a = Gamma_a / w_a - 1 (so w_a A_a = Gamma_a - w_a) the deviation
+        // equilibrium  w_a ps + w_a A_a (rho c_s^2 - c_s^2 (e_a-u).grad rho / 2)
+        //              - (e_a-u).F Gamma_a / 2
+        // is w_a (E_a + A_a R_a) with E_a = ps - (e_a-u).F / 2 and
+        // R_a = rho c_s^2 - (e_a-u).(c_s^2 grad rho + F) / 2, both affine in e_a.
         const float mu13 = mu1 - mu3, mu23 = mu2 - mu3;
         const float fbx = rho * cd.fx, fby = -rho * cd.g;
         float Fx = mu13 * gcx[0] + fbx, Fy = mu13 * gcy[0] + fby;
@@ -318,38 +324,33 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const float ugr = ux * grx + uy * gry;
         const float uF = ux * Fx + uy * Fy;
         const float ps = 0.5f * kCs2 * ugr;          // p - s
-        const float rc2 = rho * kCs2;
-        float wA[9], G[9], deq[9];
+        const float hFx = 0.5f * Fx, hFy = 0.5f * Fy;
+        const float Vx = fmaf(0.5f * kCs2, grx, hFx), Vy = fmaf(0.5f * kCs2, gry, hFy);
+        const float E0 = fmaf(0.5f, uF, ps);
+        const float R0 = fmaf(rho, kCs2, E0);        // rho c_s^2 + c_s^2 u.grad rho / 2 + u.F / 2
+        const float uu15 = -1.5f * uu;
+        float A[9], ne[9];
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             const int ex = Lat::ex[a], ey = Lat::ey[a];
-            const float wa = Lat::w[a];
             const float eu = edot(ex, ey, ux, uy);
-            const float A = 3.0f * eu + 4.5f * eu * eu - 1.5f * uu;   // Gamma_a / w_a - 1
-            wA[a] = wa * A;
-            G[a] = wa + wA[a];
-            const float egr = edot(ex, ey, grx, gry) - ugr;
-            const float eF = edot(ex, ey, Fx, Fy) - uF;
-            deq[a] = wa * ps + wA[a] * (rc2 - 0.5f * kCs2 * egr) - 0.5f * eF * G[a];
+            A[a] = fmaf(eu, fmaf(4.5f, eu, 3.0f), uu15);
+            const float R = R0 - edot(ex, ey, Vx, Vy);
+            const float E = E0 - edot(ex, ey, hFx, hFy);
+            ne[a] = fmaf(-Lat::w[a], fmaf(A[a], R, E), d[a]);
         }
-        // non-equilibrium part; its zeroth and first moments vanish exactly
-        // (u and p are the moments of this gbar), so the float32 rounding left
-        // in them is projected out: the collision then conserves the pressure
-        // and momentum moments to the rounding of small numbers instead of
-        // leaking a systematic residue every step
-        float ne[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) ne[a] = d[a] - deq[a];
-        {
-            const float m0 = ((ne[0] + ne[1]) + (ne[2] + ne[3])) + ((ne[4] + ne[5]) + (ne[6] + ne[7])) + ne[8];
-            const float mx = (ne[1] - ne[3]) + ((ne[5] - ne[7]) + (ne[8] - ne[6]));
-            const float my = (ne[2] - ne[4]) + ((ne[5] - ne[7]) + (ne[6] - ne[8]));
-#pragma unroll
-            for (int a = 0; a < 9; ++a)
-                ne[a] -= Lat::w[a] * (m0 + 3.0f * edot(Lat::ex[a], Lat::ey[a], mx, my));
-        }
+        // The zeroth and first moments of the non-equilibrium part vanish
+        // exactly (u and p are the moments of this gbar); the float32 rounding
+        // left in them, m0 and m, is projected out, ne_a -> ne_a - w_a (m0 +
+        // 3 e_a.m), so that the collision conserves the pressure and momentum
+        // moments to the rounding of small numbers instead of leaking a
+        // systematic residue every step.  The projection lowers Pi_xx and
+        // Pi_yy by c_s^2 m0 and is applied inside the collision below.
+        const float m0 = ((ne[0] + ne[1]) + (ne[2] + ne[3])) + ((ne[4] + ne[5]) + (ne[6] + ne[7])) + ne[8];
+        const float mx = (ne[1] - ne[3]) + ((ne[5] - ne[7]) + (ne[8] - ne[6]));
+        const float my = (ne[2] - ne[4]) + ((ne[5] - ne[7]) + (ne[6] - ne[8]));
         const float pdiag = ne[5] + ne[6] + ne[7] + ne[8];
-        const float pxx = ne[1] + ne[3] + pdiag, pyy = ne[2] + ne[4] + pdiag;
+        const float pxx = fmaf(-kCs2, m0, ne[1] + ne[3] + pdiag), pyy = fmaf(-kCs2, m0, ne[2] + ne[4] + pdiag);
         const float pxy = ne[5] - ne[6] + ne[7] - ne[8];
         // shear rate: D = -Pi / (2 (tau_prev + 1/2) rho c_s^4), gdot = sqrt(2 D:D)
         const float fs = 4.5f * rcp((tprev + 0.5f) * rho);
@@ -357,20 +358,30 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const float tau = mixture_tau(cd, c[0], c[1], c3, gdot);
         const float om = rcp(tau + 0.5f);
 
-        // gbar collision with the mixed-difference forcing
+        // gbar collision with the mixed-difference forcing:
+        //   d*_a = d_a - om (ne_a - w_a (m0 + 3 e_a.m)) + c_s^2 (d_a rho - u.grad^MD rho) w_a A_a
+        //          + [sum_k mu_k (d_a C_k - u.grad^MD C_k) + (e_a-u).F_b] w_a (1 + A_a)
+        //        = d_a - om ne_a + w_a [Z_a + t_a + A_a (K_a + t_a)]
         const float umr = ux * mrx + uy * mry;
         const float um1 = ux * mcx[0] + uy * mcy[0], um2 = ux * mcx[1] + uy * mcy[1];
-        const float ufb = ux * fbx + uy * fby;
+        float T0 = -(ux * fbx + uy * fby) - mu13 * um1;
+        if (NH == 2) T0 -= mu23 * um2;
+        const float Z0 = om * m0, Zx = 3.0f * om * mx, Zy = 3.0f * om * my;
+        const float cum = -kCs2 * umr;
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            const float t1 = kCs2 * (drho[a] - umr) * wA[a];
-            float t2 = mu13 * (dc[0][a] - um1) + (edot(Lat::ex[a], Lat::ey[a], fbx, fby) - ufb);
-            if (NH == 2) t2 += mu23 * (dc[1][a] - um2);
-            sD[a][idx] = d[a] - om * ne[a] + (t1 + t2 * G[a]);
+            const int ex = Lat::ex[a], ey = Lat::ey[a];
+            const float K = fmaf(kCs2, drho[a], cum);
+            float t = fmaf(mu13, dc[0][a], T0 + edot(ex, ey, fbx, fby));
+            if (NH == 2) t = fmaf(mu23, dc[1][a], t);
+            const float br = fmaf(A[a], K + t, (Z0 + edot(ex, ey, Zx, Zy)) + t);
+            sD[a][idx] = fmaf(Lat::w[a], br, fmaf(-om, ne[a], d[a]));
         }
 
         // hbar collision: equilibrium with central differences, forcing with the
-        // mixed derivative of C_i and central grad p, source half of Dif
+        // mixed derivative of C_i and central grad p, source half of Dif.
+        //   X = grad C_i - (C_i / (rho c_s^2)) (grad p - F),
+        //   forcing (d_a C_i - u.grad^MD C_i) - (C_i/(rho c_s^2)) (e_a-u).(grad p - F)
         const float bx = gpx - Fx, by = gpy - Fy;
         const float ub = ux * bx + uy * by;
         const float r3 = 3.0f * rcp(rho);
@@ -380,17 +391,25 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             const float Xx = gcx[i] - kk * bx, Xy = gcy[i] - kk * by;
             const float uX = ux * Xx + uy * Xy;
             const float umc = (i == 0) ? um1 : um2;
+            if (SH) {
+                // hbar* - (1 - omega_h) hbar = Gamma_a [omega_h (C - (e_a-u).X / 2) + forcing + Dif / 2]
+                const float oh = cd.omh;
+                const float H0 = fmaf(oh, fmaf(0.5f, uX, c[i]), fmaf(kk, ub, 0.5f * dif[i]) - umc);
+                const float Hx = fmaf(0.5f * oh, Xx, kk * bx), Hy = fmaf(0.5f * oh, Xy, kk * by);
 #pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                const int ex = Lat::ex[a], ey = Lat::ey[a];
-                const float eX = edot(ex, ey, Xx, Xy) - uX;
-                const float fX = (dc[i][a] - umc) - kk * (edot(ex, ey, bx, by) - ub);
-                if (SH) {
-                    const float heq = c[i] * G[a] - 0.5f * eX * G[a];
-                    sH[i][a][idx] = cd.omh * heq + fX * G[a] + 0.5f * dif[i] * G[a];
-                } else {
-                    // omega_h = 1: hbar* - w_a C = w_a A_a C + (-(e-u).X/2 + (e-u).X^MD + Dif/2) Gamma_a
-                    sH[i][a][idx] = wA[a] * c[i] + (-0.5f * eX + fX + 0.5f * dif[i]) * G[a];
+                for (int a = 0; a < 9; ++a) {
+                    const float H = (H0 + dc[i][a]) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
+                    sH[i][a][idx] = Lat::w[a] * (1.0f + A[a]) * H;
+                }
+            } else {
+                // omega_h = 1: hbar* - w_a C = w_a A_a C + Gamma_a H_a
+                //   = w_a [H_a + A_a (C + H_a)],  H_a = -(e_a-u).X / 2 + forcing + Dif / 2
+                const float H0 = fmaf(0.5f, uX, fmaf(kk, ub, 0.5f * dif[i])) - umc;
+                const float Hx = fmaf(0.5f, Xx, kk * bx), Hy = fmaf(0.5f, Xy, kk * by);
+#pragma unroll
+                for (int a = 0; a < 9; ++a) {
+                    const float H = (H0 + dc[i][a]) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
+                    sH[i][a][idx] = Lat::w[a] * fmaf(A[a], c[i] + H, H);
                 }
             }
             sDif[i][idx] = dif[i];
