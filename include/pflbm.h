@@ -101,7 +101,7 @@ size_t pflbm_workspace_bytes(const pflbm_params* cases, int32_t ncases);
  * (nx or ny < 5, n_h not 1 or 2, rho_k <= 0, nu_k <= 0, nu_min <= 0 or
  * nu_min > nu_max, K <= 0 with a power-law component, xi <= 0, D0 < 0,
  * tau_h <= 0, a Sigma_i <= 0, store_h = 0 with tau_h != 0.5, storage not
- * 0 or 1); UNSUPPORTED for storage = 1 with store_h = 1; WORKSPACE when the
+ * 0 or 1, nx rounded up to 64 times ny at or above 2^29 nodes); UNSUPPORTED for storage = 1 with store_h = 1; WORKSPACE when the
  * workspace is NULL, small or misaligned; DEVICE when a HIP call fails.
  */
 int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspace, size_t bytes,

@@ -161,6 +161,23 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
     return (__attribute__((address_space(1))) T*)p;
 }
 
+// Global access at a uniform base plus a 32-bit byte offset: the compiler
+// then uses the SGPR-base form of the global load/store, so one 32-bit offset
+// per node serves every plane (no 64-bit address arithmetic per access).
+// Every plane of a case is below 4 GiB (checked when the context is created).
+template <class T>
+__device__ __forceinline__ T gld(const T* base, uint32_t boff) {
+    typedef const __attribute__((address_space(1))) char* gcp;
+    typedef const __attribute__((address_space(1))) T* gtp;
+    return *(gtp)((gcp)base + boff);
+}
+template <class T>
+__device__ __forceinline__ void gst(T* base, uint32_t boff, T v) {
+    typedef __attribute__((address_space(1))) char* gcp;
+    typedef __attribute__((address_space(1))) T* gtp;
+    *(gtp)((gcp)base + boff) = v;
+}
+
 // Chemical potentials of the ternary free energy (Sec. 2.1, Eqs. (3), (5)):
 // mu_i = sum_{j != i} (dE0/dC_i - dE0/dC_j) a_j - (3/4) xi Sigma_i lap C_i
 // with a_j = 4 Sigma_T / (xi Sigma_j).  The bulk part is evaluated in float64

@@ -49,6 +49,8 @@ bool is_finite(double v) { return isfinite(v) != 0; }
 
 bool valid_params(const pflbm_params& p) {
     if (p.nx < 5 || p.ny < 5 || (p.n_h != 1 && p.n_h != 2)) return false;
+    // kernels address a plane with 32-bit byte offsets: float64 planes < 4 GiB
+    if ((double)align_up((size_t)p.nx, kPitchElems) * (double)p.ny * 8.0 >= 4294967296.0) return false;
     if ((long long)p.nx * p.ny > (1LL << 31)) return false;
     for (int k = 0; k < 3; ++k)
         if (!(p.rho[k] > 0.0) || !(p.nu[k] > 0.0) || !is_finite(p.rho[k]) || !is_finite(p.nu[k])) return false;

@@ -19,6 +19,8 @@
 // gbar is carried as s = sum gbar plus deviations d_a = gbar_a - w_a s so that
 // the momentum moment is formed from small numbers (float32 at density
 // ratio 1000).
+#include <type_traits>
+
 #include "pflbm_internal.h"
 
 namespace pflbm {
@@ -99,16 +101,16 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     const int nx = cd.nx, ny = cd.ny, pitch = cd.pitch;
     const long long plane = cd.plane;
     const int x0 = tile.x0, y0 = tile.y0;
-    const auto Sin = gmem<const float>(cd.S[par]);
-    const auto Cin = gmem<const double>(cd.C[par]);
-    const auto Tin = gmem<const float>(cd.T[par]);
-    const auto Sout = gmem<float>(cd.S[par ^ 1]);
-    const auto Cout = gmem<double>(cd.C[par ^ 1]);
-    const auto Tout = gmem<float>(cd.T[par ^ 1]);
-    const auto Hin = gmem<const float>(cd.H[par]);
-    const auto Hout = gmem<float>(cd.H[par ^ 1]);
-    const auto Qin = gmem<const _Float16>(cd.Q[par]);
-    const auto Qout = gmem<_Float16>(cd.Q[par ^ 1]);
+    const float* Sin = cd.S[par];
+    const double* Cin = cd.C[par];
+    const float* Tin = cd.T[par];
+    float* Sout = cd.S[par ^ 1];
+    double* Cout = cd.C[par ^ 1];
+    float* Tout = cd.T[par ^ 1];
+    const float* Hin = cd.H[par];
+    float* Hout = cd.H[par ^ 1];
+    const _Float16* Qin = cd.Q[par];
+    _Float16* Qout = cd.Q[par ^ 1];
     const float qinv = cd.qinv, qscale = cd.qscale;
     const int tid = threadIdx.x;
 
@@ -119,37 +121,48 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     // The loads are unconditional (surplus threads and rows beyond the walls
     // read a valid node and discard it) so that no branch forces an early wait.
     constexpr int KA = (N3 + NT - 1) / NT, KB = (N2 + NT - 1) / NT;
-    double ca[KA][NH];
-#pragma unroll
-    for (int k = 0; k < KA; ++k) {
-        const int idx = min(tid + k * NT, N3 - 1);
-        const int ry = idx / W3, rx = idx - ry * W3;
-        const int gx = wrap_x_tile(x0 - 3 + rx, nx), gy = mirror_y(y0 - 3 + ry, ny);
-        const long long off = (long long)gy * pitch + gx;
-#pragma unroll
-        for (int i = 0; i < NH; ++i) ca[k][i] = Cin[i * plane + off];
-    }
-    // gbar state of the R2 nodes: s, the momentum and (used for the R1 nodes)
-    // the rest of the deviations and tau
     constexpr int ND = F16 ? 2 + kQPlanes : 8;
+    double ca[KA][NH];
     float ps[KB], pd[KB][ND], pt[KB];
+    // Element offset of region node (rx, ry) of the region with halo h: tiles
+    // whose regions stay clear of the walls and of the periodic seam take the
+    // plain offset, the others wrap x and mirror y.
+    auto loads = [&](auto plain_tag) {
+        constexpr bool PLAIN = decltype(plain_tag)::value;
+        auto node = [&](int rx, int ry, int h) -> uint32_t {
+            if (PLAIN) return (uint32_t)((y0 - h + ry) * pitch + (x0 - h + rx));
+            return (uint32_t)(mirror_y(y0 - h + ry, ny) * pitch + wrap_x_tile(x0 - h + rx, nx));
+        };
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-        const int idx = min(tid + k * NT, N2 - 1);
-        const int ry = idx / W2, rx = idx - ry * W2;
-        const long long off = (long long)mirror_y(y0 - 2 + ry, ny) * pitch + wrap_x_tile(x0 - 2 + rx, nx);
-        ps[k] = Sin[off];
-        if (F16) {
-            pd[k][0] = Sin[plane + off];
-            pd[k][1] = Sin[2 * plane + off];
+        for (int k = 0; k < KA; ++k) {
+            const int idx = min(tid + k * NT, N3 - 1);
+            const int ry = idx / W3, rx = idx - ry * W3;
+            const uint32_t eo = node(rx, ry, 3);
 #pragma unroll
-            for (int q = 0; q < kQPlanes; ++q) pd[k][2 + q] = (float)Qin[q * plane + off];
-        } else {
-#pragma unroll
-            for (int a = 1; a < 9; ++a) pd[k][a - 1] = Sin[a * plane + off];
+            for (int i = 0; i < NH; ++i) ca[k][i] = gld(Cin + i * plane, eo * 8u);
         }
-        pt[k] = Tin[off];
-    }
+        // gbar state of the R2 nodes: s, the momentum and (used for the R1
+        // nodes) the rest of the deviations and tau
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int idx = min(tid + k * NT, N2 - 1);
+            const int ry = idx / W2, rx = idx - ry * W2;
+            const uint32_t eo = node(rx, ry, 2);
+            ps[k] = gld(Sin, eo * 4u);
+            if (F16) {
+                pd[k][0] = gld(Sin + plane, eo * 4u);
+                pd[k][1] = gld(Sin + 2 * plane, eo * 4u);
+#pragma unroll
+                for (int q = 0; q < kQPlanes; ++q) pd[k][2 + q] = (float)gld(Qin + q * plane, eo * 2u);
+            } else {
+#pragma unroll
+                for (int a = 1; a < 9; ++a) pd[k][a - 1] = gld(Sin + a * plane, eo * 4u);
+            }
+            pt[k] = gld(Tin, eo * 4u);
+        }
+    };
+    if (x0 >= 3 && x0 + TX + 3 <= nx && y0 >= 3 && y0 + TY + 3 <= ny) loads(std::true_type{});
+    else loads(std::false_type{});
     // surplus threads (idx >= N3) repeat node N3 - 1: same address, same value
 #pragma unroll
     for (int k = 0; k < KA; ++k) {
@@ -250,8 +263,6 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         if (gyr < 0 || gyr >= ny) continue;   // nodes beyond the walls are never sources
         const int i2 = (ry + 1) * W2 + rx + 1;
         const int i3 = (ry + 2) * W3 + rx + 2;
-        const int gx = wrap_x_tile(x0 - 1 + rx, nx);
-        const long long off = (long long)gyr * pitch + gx;
 
         float d[9];
 #pragma unroll
@@ -416,90 +427,102 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         }
         // tau is written for the tile's own nodes
         const int ox = rx - 1, oy = ry - 1;
-        if (ox >= 0 && ox < TX && oy >= 0 && oy < TY && x0 + ox < nx) Tout[off] = tau;
+        if (ox >= 0 && ox < TX && oy >= 0 && oy < TY && x0 + ox < nx)
+            gst(Tout, (uint32_t)(gyr * pitch + x0 + ox) * 4u, tau);
     }
     __syncthreads();
 
-    // ---------------- phase D: gather, bounce-back, destination term, write
-    for (int idx = tid; idx < TX * TY; idx += NT) {
-        const int oy = idx / TX, ox = idx - oy * TX;
-        const int gx = x0 + ox, gyr = y0 + oy;
-        if (gx >= nx || gyr >= ny) continue;
-        const int i1 = (oy + 1) * W1 + ox + 1;
-        const int i2 = (oy + 2) * W2 + ox + 2;
-        const long long off = (long long)gyr * pitch + gx;
-        float sv[9], dv[9];
-        int src[9], dir[9];
+    // ---------------- phase D: gather, bounce-back, destination term, write.
+    // Only tiles holding row 0 or row ny-1 have bounced populations; the
+    // others take the gather offsets as compile-time constants.
+    auto phase_d = [&](auto wall_tag) {
+        constexpr bool WALL = decltype(wall_tag)::value;
+        for (int idx = tid; idx < TX * TY; idx += NT) {
+            const int oy = idx / TX, ox = idx - oy * TX;
+            const int gx = x0 + ox, gyr = y0 + oy;
+            if (gx >= nx || gyr >= ny) continue;
+            const int i1 = (oy + 1) * W1 + ox + 1;
+            const int i2 = (oy + 2) * W2 + ox + 2;
+            const uint32_t eo = (uint32_t)(gyr * pitch + gx);
+            float sv[9], dv[9];
+            int src[9], dir[9];
+            bool bb[9];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const int sy = gyr - Lat::ey[a];
-            if (sy < 0 || sy >= ny) { src[a] = i1; dir[a] = Lat::opp[a]; }
-            else { src[a] = i1 - Lat::ey[a] * W1 - Lat::ex[a]; dir[a] = a; }
-        }
-        // s(y) = sum_a w_a s(z_a) + sum_a d*_a(z_a), formed around the node's own
-        // s with sum_a w_a = 1 taken exactly (the float32 weights sum to
-        // 1 + 8e-9, which would inflate the pressure level every step)
-        const float sy0 = sS[i1];
-        float ssum = 0.f, dsum = 0.f;
+            for (int a = 0; a < 9; ++a) {
+                const int sy = gyr - Lat::ey[a];
+                bb[a] = WALL && (sy < 0 || sy >= ny);
+                src[a] = bb[a] ? i1 : i1 - Lat::ey[a] * W1 - Lat::ex[a];
+                dir[a] = bb[a] ? Lat::opp[a] : a;
+            }
+            // s(y) = sum_a w_a s(z_a) + sum_a d*_a(z_a), formed around the node's
+            // own s with sum_a w_a = 1 taken exactly (the float32 weights sum to
+            // 1 + 8e-9, which would inflate the pressure level every step)
+            const float sy0 = sS[i1];
+            float ssum = 0.f, dsum = 0.f;
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            sv[a] = sS[src[a]];
-            dv[a] = sD[dir[a]][src[a]];
-            if (a > 0 && dir[a] == a) ssum += Lat::w[a] * (sv[a] - sy0);
-            dsum += dv[a];
-        }
-        const float snew = sy0 + (ssum + dsum);
-        Sout[off] = snew;
-        if (F16) {
-            float da[9], jx, jy, m[kQPlanes];
+            for (int a = 0; a < 9; ++a) {
+                sv[a] = sS[src[a]];
+                dv[a] = sD[dir[a]][src[a]];
+                if (a > 0 && !bb[a]) ssum += Lat::w[a] * (sv[a] - sy0);
+                dsum += dv[a];
+            }
+            const float snew = sy0 + (ssum + dsum);
+            gst(Sout, eo * 4u, snew);
+            if (F16) {
+                float da[9], jx, jy, m[kQPlanes];
 #pragma unroll
-            for (int a = 1; a < 9; ++a) da[a] = Lat::w[a] * (sv[a] - snew) + dv[a];
-            pack_devs(da, jx, jy, m);
-            Sout[plane + off] = jx;
-            Sout[2 * plane + off] = jy;
+                for (int a = 1; a < 9; ++a) da[a] = Lat::w[a] * (sv[a] - snew) + dv[a];
+                pack_devs(da, jx, jy, m);
+                gst(Sout + plane, eo * 4u, jx);
+                gst(Sout + 2 * plane, eo * 4u, jy);
 #pragma unroll
-            for (int k = 0; k < kQPlanes; ++k) Qout[k * plane + off] = (_Float16)(m[k] * qscale);   // nearest even
-        } else {
-#pragma unroll
-            for (int a = 1; a < 9; ++a) Sout[a * plane + off] = Lat::w[a] * (sv[a] - snew) + dv[a];
-        }
-
-        // region index of the output node and of each source on R3 (for C)
-        const int j3 = (oy + 3) * W3 + ox + 3;
-#pragma unroll
-        for (int i = 0; i < NH; ++i) {
-            const float hd = 0.5f * sDif[i][i1];
-            if (SH) {
-                const float ux = sUx[i2], uy = sUy[i2], uu = ux * ux + uy * uy;
-                float csum = 0.f;
-#pragma unroll
-                for (int a = 0; a < 9; ++a) {
-                    const float eu = Lat::ex[a] * ux + Lat::ey[a] * uy;
-                    const float G = Lat::w[a] * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
-                    float hv = sH[i][dir[a]][src[a]] + hd * G;
-                    const int sxg = wrap_x(gx - (dir[a] == a ? Lat::ex[a] : 0), nx);
-                    const int syg = dir[a] == a ? gyr - Lat::ey[a] : gyr;
-                    const long long so = (long long)syg * pitch + sxg;
-                    hv += (1.0f - cd.omh) * Hin[(long long)(i * 9 + dir[a]) * plane + so];
-                    Hout[(long long)(i * 9 + a) * plane + off] = hv;
-                    csum += hv;
-                }
-                Cout[(long long)i * plane + off] = (double)csum;
+                for (int k = 0; k < kQPlanes; ++k)
+                    gst(Qout + k * plane, eo * 2u, (_Float16)(m[k] * qscale));   // nearest even
             } else {
-                // C(t+1) = C(y) + sum_a [w_a (C(z_a) - C(y)) + (hbar*_b(z_a) - w_b C(z_a))] + Dif(y)/2 sum_a Gamma_a(y)
-                // (sum_a Gamma_a = 1 exactly for D2Q9)
-                const double cy = sCd[i][j3];
-                double dsum = 0.0;
-                float qsum = 0.f;
 #pragma unroll
-                for (int a = 0; a < 9; ++a) {
-                    qsum += sH[i][dir[a]][src[a]];
-                    if (a > 0 && dir[a] == a) dsum += (double)Lat::w[a] * (sCd[i][j3 - Lat::ey[a] * W3 - Lat::ex[a]] - cy);
+                for (int a = 1; a < 9; ++a) gst(Sout + a * plane, eo * 4u, Lat::w[a] * (sv[a] - snew) + dv[a]);
+            }
+
+            // region index of the output node and of each source on R3 (for C)
+            const int j3 = (oy + 3) * W3 + ox + 3;
+#pragma unroll
+            for (int i = 0; i < NH; ++i) {
+                const float hd = 0.5f * sDif[i][i1];
+                if (SH) {
+                    const float ux = sUx[i2], uy = sUy[i2], uu = ux * ux + uy * uy;
+                    float csum = 0.f;
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) {
+                        const float eu = Lat::ex[a] * ux + Lat::ey[a] * uy;
+                        const float G = Lat::w[a] * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
+                        float hv = sH[i][dir[a]][src[a]] + hd * G;
+                        const int sxg = wrap_x(gx - (bb[a] ? 0 : Lat::ex[a]), nx);
+                        const int syg = bb[a] ? gyr : gyr - Lat::ey[a];
+                        const uint32_t so = (uint32_t)(syg * pitch + sxg);
+                        hv += (1.0f - cd.omh) * gld(Hin + (i * 9 + dir[a]) * plane, so * 4u);
+                        gst(Hout + (i * 9 + a) * plane, eo * 4u, hv);
+                        csum += hv;
+                    }
+                    gst(Cout + i * plane, eo * 8u, (double)csum);
+                } else {
+                    // C(t+1) = C(y) + sum_a [w_a (C(z_a) - C(y)) + (hbar*_b(z_a) - w_b C(z_a))]
+                    //          + Dif(y)/2 sum_a Gamma_a(y)      (sum_a Gamma_a = 1 exactly for D2Q9)
+                    const double cy = sCd[i][j3];
+                    double dsum = 0.0;
+                    float qsum = 0.f;
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) {
+                        qsum += sH[i][dir[a]][src[a]];
+                        if (a > 0 && !bb[a])
+                            dsum += (double)Lat::w[a] * (sCd[i][j3 - Lat::ey[a] * W3 - Lat::ex[a]] - cy);
+                    }
+                    gst(Cout + i * plane, eo * 8u, cy + (dsum + (double)(qsum + hd)));
                 }
-                Cout[(long long)i * plane + off] = cy + (dsum + (double)(qsum + hd));
             }
         }
-    }
+    };
+    if (y0 == 0 || y0 + TY >= ny) phase_d(std::true_type{});
+    else phase_d(std::false_type{});
 }
 
 // Step variants selectable at run time: tile shape x phase-field count x
