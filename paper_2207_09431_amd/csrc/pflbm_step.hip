@@ -210,8 +210,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
                 jx = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
                 jy = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
             }
-            if (rx >= 1 && rx <= W2 - 2 && ry >= 1 && ry <= H2 - 2) {
-                const int i1 = (ry - 1) * W1 + rx - 1;
+            const bool in_r1 = rx >= 1 && rx <= W2 - 2 && ry >= 1 && ry <= H2 - 2;
+            const int i1 = (ry - 1) * W1 + rx - 1;
+            if (in_r1) {
                 if (F16) {
                     float m[kQPlanes];
 #pragma unroll
@@ -238,6 +239,20 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             const float uy = (3.0f * jy + 0.5f * fy) * rr;
             sUx[idx] = ux;
             sUy[idx] = uy;
+            if (in_r1) {
+                // grad C_i, grad rho and the force of the R1 nodes, parked in
+                // the hbar planes (written only later, by phase C)
+                sH[0][0][i1] = gcx[0];
+                sH[0][1][i1] = gcy[0];
+                sH[0][2][i1] = grx;
+                sH[0][3][i1] = gry;
+                sH[0][4][i1] = fx;
+                sH[0][5][i1] = fy;
+                if (NH == 2) {
+                    sH[0][6][i1] = gcx[1];
+                    sH[0][7][i1] = gcy[1];
+                }
+            }
             sP[idx] = s + 0.5f * kCs2 * (ux * grx + uy * gry);
         }
     }
@@ -271,17 +286,22 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         d[0] = -(d[1] + d[2] + d[3] + d[4] + d[5] + d[6] + d[7] + d[8]);
         const float tprev = sDif[0][idx];
 
-        // central gradients of C_i and rho, moments and potentials of the node
+        // central gradients of C_i and rho and the force (parked by phase B),
+        // moments and potentials of the node
         float c[2] = {0.f, 0.f}, gcx[2] = {0.f, 0.f}, gcy[2] = {0.f, 0.f};
 #pragma unroll
-        for (int i = 0; i < NH; ++i) {
-            c[i] = sC[i][i3];
-            cd_grad<W3>(sC[i], i3, gcx[i], gcy[i]);
+        for (int i = 0; i < NH; ++i) c[i] = sC[i][i3];
+        gcx[0] = sH[0][0][idx];
+        gcy[0] = sH[0][1][idx];
+        if (NH == 2) {
+            gcx[1] = sH[0][6][idx];
+            gcy[1] = sH[0][7][idx];
         }
+        const float grx = sH[0][2][idx], gry = sH[0][3][idx];
+        const float Fx = sH[0][4][idx], Fy = sH[0][5][idx];
         const float c3 = 1.0f - c[0] - c[1];
         const float rho = sR[i3];
-        float grx, gry, gpx, gpy;
-        cd_grad<W3>(sR, i3, grx, gry);
+        float gpx, gpy;
         cd_grad<W2>(sP, i2, gpx, gpy);
         const float mu1 = sMu[0][i2], mu3 = sMu[NH][i2];
         const float mu2 = NH == 2 ? sMu[1][i2] : 0.0f;
@@ -326,11 +346,6 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         // R_a = rho c_s^2 - (e_a-u).(c_s^2 grad rho + F) / 2, both affine in e_a.
         const float mu13 = mu1 - mu3, mu23 = mu2 - mu3;
         const float fbx = rho * cd.fx, fby = -rho * cd.g;
-        float Fx = mu13 * gcx[0] + fbx, Fy = mu13 * gcy[0] + fby;
-        if (NH == 2) {
-            Fx += mu23 * gcx[1];
-            Fy += mu23 * gcy[1];
-        }
         const float uu = ux * ux + uy * uy;
         const float ugr = ux * grx + uy * gry;
         const float uF = ux * Fx + uy * Fy;
