@@ -82,8 +82,8 @@ typedef struct {
  *    collision relaxes.  Requires store_h = 0.
  *  - store_h = 0 (requires tau_h = 0.5): hbar relaxes at rate 1, so the
  *    post-collision hbar depends only on time-t fields and keeping C_i alone
- *    is exact.  store_h = 1 keeps the 9 n_h hbar planes (float32), for any
- *    tau_h.
+ *    is exact.  store_h = 1 keeps hbar as 9 n_h float32 planes of the
+ *    deviations hbar_a - w_a C_i (C_i itself stays float64), for any tau_h.
  */
 
 /*

@@ -149,7 +149,8 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const CaseDev* __restrict_
             for (int a = 0; a < 9; ++a) {
                 const float G = Lat::w[a] * (1.0f + A[a]);
                 const float eX = Lat::ex[a] * Xx + Lat::ey[a] * Xy - uX;
-                cd.H[par][(long long)(i * 9 + a) * cd.plane + off] = st.c[i] * G - 0.5f * eX * G;
+                // stored as the deviation q_a = hbar_a - w_a C of the equilibrium
+                cd.H[par][(long long)(i * 9 + a) * cd.plane + off] = st.c[i] * Lat::w[a] * A[a] - 0.5f * eX * G;
             }
         }
     }
@@ -216,7 +217,10 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(const CaseDev* __restric
         NodeStencil st;
         float ux, uy, pp;
         node_macro(cd, par, x, y, st, ux, uy, pp);
-        const double cg = comp == 2 ? (double)(1.0f - st.c[0] - st.c[1]) : (double)st.c[comp];
+        // the phase fields in float64, straight from the state (unclipped)
+        const long long off = (long long)y * cd.pitch + x;
+        const double c1 = cd.C[par][off], c2 = cd.n_h == 2 ? cd.C[par][cd.plane + off] : 0.0;
+        const double cg = comp == 0 ? c1 : (comp == 1 ? c2 : 1.0 - c1 - c2);
         acc[0].add(cg);
         if (cg > 0.5) acc[1].add(cg);
         acc[2].add(cg * x);

@@ -11,12 +11,18 @@
 namespace pflbm {
 
 // D2Q9 in the order of Sec. 2.2, Eq. (11): 0 rest, 1-4 axes, 5-8 diagonals.
+// The float32 weights are 4/9 and 1/9 rounded to nearest and 1/36 one unit
+// in the last place below its nearest value (0x3CE38E38 instead of
+// 0x3CE38E39), so that they sum to exactly 1: with the nearest values the
+// sum is 1 + 7.45e-9, and every source term whose weighted sum is meant to
+// return its own value (sum_a Gamma_a H = H) gains 7.45e-9 H per node and
+// step, a systematic drift of the component mass.
 struct Lat {
     static constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     static constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
     static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
     static constexpr float w[9] = {4.0f / 9.0f, 1.0f / 9.0f, 1.0f / 9.0f, 1.0f / 9.0f, 1.0f / 9.0f,
-                                   1.0f / 36.0f, 1.0f / 36.0f, 1.0f / 36.0f, 1.0f / 36.0f};
+                                   0x1.c71c7p-6f, 0x1.c71c7p-6f, 0x1.c71c7p-6f, 0x1.c71c7p-6f};
 };
 constexpr float kCs2 = 1.0f / 3.0f;
 
@@ -34,7 +40,7 @@ struct CaseDev {
     float* S[2];        // 9 planes each (ping-pong)
     double* C[2];       // n_h planes each (float64)
     float* T[2];        // tau of the previous step
-    float* H[2];        // 9*n_h planes each when hbar is stored, else null
+    float* H[2];        // stored-hbar form: q_a = hbar_a - w_a C_i, 9*n_h planes each, else null
     // float16 storage form: S holds s, j_x, j_y (float32) and Q the six pair
     // moments of the deviations (float16, scaled by qscale); null otherwise
     _Float16* Q[2];

@@ -51,6 +51,24 @@ __device__ __forceinline__ float edot(int ex, int ey, float vx, float vy) {
     const float t = ex > 0 ? vx : -vx;
     return ey > 0 ? t + vy : t - vy;
 }
+// The same from the float64 phase field: near C = 1 the float32 copy is
+// spaced 6e-8, which the 5/4-weighted stencil turns into derivative noise of
+// that size, a random walk of the component mass and a velocity error at the
+// bubble rims; the stencil is therefore taken in float64 and rounded once.
+template <int W>
+__device__ __forceinline__ void md_all_d(const double* f, int i, float d[9], float& gx, float& gy) {
+    d[0] = 0.0f;
+    const double fc = -0.75 * f[i];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        const int o = Lat::ey[a] * W + Lat::ex[a];
+        d[a] = (float)fma(0.25, fma(5.0, f[i + o], -f[i + 2 * o]) - f[i - o], fc);
+    }
+    const float p5 = d[5] - d[7], p6 = d[6] - d[8];
+    gx = (1.0f / 3.0f) * (d[1] - d[3]) + (1.0f / 12.0f) * (p5 - p6);
+    gy = (1.0f / 3.0f) * (d[2] - d[4]) + (1.0f / 12.0f) * (p5 + p6);
+}
+
 // Mixed directional derivatives along e_1..e_8 (mean of the central and the
 // second-order biased differences) and the mixed gradient
 // grad^MD f = sum_a w_a e_a d_a f / c_s^2 built from them.
@@ -332,7 +350,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         float drho[9], dc[2][9], mrx, mry, mcx[2] = {0.f, 0.f}, mcy[2] = {0.f, 0.f};
         md_all<W3>(sR, i3, drho, mrx, mry);
 #pragma unroll
-        for (int i = 0; i < NH; ++i) md_all<W3>(sC[i], i3, dc[i], mcx[i], mcy[i]);
+        for (int i = 0; i < NH; ++i) md_all_d<W3>(sCd[i], i3, dc[i], mcx[i], mcy[i]);
         if (NH == 1) {
 #pragma unroll
             for (int a = 0; a < 9; ++a) dc[1][a] = 0.0f;
@@ -418,14 +436,18 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             const float uX = ux * Xx + uy * Xy;
             const float umc = (i == 0) ? um1 : um2;
             if (SH) {
-                // hbar* - (1 - omega_h) hbar = Gamma_a [omega_h (C - (e_a-u).X / 2) + forcing + Dif / 2]
+                // stored hbar_a = w_a C + q_a: hbar*_a = w_a C + (1 - omega_h) q_a + Q_a with
+                //   Q_a = omega_h w_a A_a C + Gamma_a [-omega_h (e_a-u).X / 2 + forcing + Dif / 2]
+                //       = w_a [H_a + A_a (omega_h C + H_a)];  Q_a is parked, the q_a term is
+                // added by the receiver, and w_a C streams in float64 there
                 const float oh = cd.omh;
-                const float H0 = fmaf(oh, fmaf(0.5f, uX, c[i]), fmaf(kk, ub, 0.5f * dif[i]) - umc);
+                const float H0 = fmaf(0.5f * oh, uX, fmaf(kk, ub, 0.5f * dif[i])) - umc;
                 const float Hx = fmaf(0.5f * oh, Xx, kk * bx), Hy = fmaf(0.5f * oh, Xy, kk * by);
+                const float oc = oh * c[i];
 #pragma unroll
                 for (int a = 0; a < 9; ++a) {
                     const float H = (H0 + dc[i][a]) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
-                    sH[i][a][idx] = Lat::w[a] * (1.0f + A[a]) * H;
+                    sH[i][a][idx] = Lat::w[a] * fmaf(A[a], oc + H, H);
                 }
             } else {
                 // omega_h = 1: hbar* - w_a C = w_a A_a C + Gamma_a H_a
@@ -504,21 +526,29 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             for (int i = 0; i < NH; ++i) {
                 const float hd = 0.5f * sDif[i][i1];
                 if (SH) {
+                    // hbar_a(y) = w_a C(z_a) + (1 - omega_h) q_b(z_a) + Q_b(z_a) + Dif(y)/2 Gamma_a(y);
+                    // C(t+1) = sum_a hbar_a(y) accumulated in float64 around C(y), and the
+                    // new deviations q_a = hbar_a - w_a C(t+1)
                     const float ux = sUx[i2], uy = sUy[i2], uu = ux * ux + uy * uy;
-                    float csum = 0.f;
+                    const double cy = sCd[i][j3];
+                    float hv[9];
+                    double dz[9], csum = 0.0;
 #pragma unroll
                     for (int a = 0; a < 9; ++a) {
                         const float eu = Lat::ex[a] * ux + Lat::ey[a] * uy;
                         const float G = Lat::w[a] * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
-                        float hv = sH[i][dir[a]][src[a]] + hd * G;
                         const int sxg = wrap_x(gx - (bb[a] ? 0 : Lat::ex[a]), nx);
                         const int syg = bb[a] ? gyr : gyr - Lat::ey[a];
                         const uint32_t so = (uint32_t)(syg * pitch + sxg);
-                        hv += (1.0f - cd.omh) * gld(Hin + (i * 9 + dir[a]) * plane, so * 4u);
-                        gst(Hout + (i * 9 + a) * plane, eo * 4u, hv);
-                        csum += hv;
+                        hv[a] = sH[i][dir[a]][src[a]] + (1.0f - cd.omh) * gld(Hin + (i * 9 + dir[a]) * plane, so * 4u) +
+                                hd * G;
+                        dz[a] = bb[a] ? 0.0 : sCd[i][j3 - Lat::ey[a] * W3 - Lat::ex[a]] - cy;
+                        csum += (double)Lat::w[a] * dz[a] + (double)hv[a];
                     }
-                    gst(Cout + i * plane, eo * 8u, (double)csum);
+                    gst(Cout + i * plane, eo * 8u, cy + csum);
+#pragma unroll
+                    for (int a = 0; a < 9; ++a)
+                        gst(Hout + (i * 9 + a) * plane, eo * 4u, (float)((double)Lat::w[a] * (dz[a] - csum) + (double)hv[a]));
                 } else {
                     // C(t+1) = C(y) + sum_a [w_a (C(z_a) - C(y)) + (hbar*_b(z_a) - w_b C(z_a))]
                     //          + Dif(y)/2 sum_a Gamma_a(y)      (sum_a Gamma_a = 1 exactly for D2Q9)
