@@ -69,6 +69,32 @@
 
 #include "pfo.h"
 
+/* Per-node loops are split over rows with OpenMP when the library is built
+ * with it.  Each node is computed by one thread with the same operations, so
+ * the results do not depend on the thread count.  (Testing only: speed.) */
+#ifdef _OPENMP
+#include <omp.h>
+#define OMP_FOR _Pragma("omp parallel for schedule(static)")
+#else
+#define OMP_FOR
+#endif
+
+void pfo_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int pfo_get_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* D2Q9 lattice, Sec. 2.2 Eqs. (10)-(11): alpha = 0 rest, 1-4 axes, 5-8 diagonals. */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -313,6 +339,7 @@ void pfo_destroy(pfo_ctx *c) {
  * (Eq. (1)), C_2 = 0 when only one phase field is carried, rho (R3). */
 static void stage_phase(pfo_ctx *c) {
     int n = c->n, nh = c->p.n_h;
+    OMP_FOR
     for (int q = 0; q < n; ++q) {
         double ci[2] = {0.0, 0.0};
         for (int i = 0; i < nh; ++i) {
@@ -332,7 +359,9 @@ static void stage_chem(pfo_ctx *c) {
     int nx = c->nx, ny = c->ny, n = c->n;
     for (int k = 0; k < 3; ++k) {
         const double *f = c->C + (size_t)k * n;
+        OMP_FOR
         for (int q = 0; q < n; ++q) c->tmp[q] = mobility_shape(f[q]);
+        OMP_FOR
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 int q = y * nx + x;
@@ -341,6 +370,7 @@ static void stage_chem(pfo_ctx *c) {
                 grad_cd_at(c->tmp, x, y, nx, ny, &c->gradM[(2 * k) * n + q], &c->gradM[(2 * k + 1) * n + q]);
             }
     }
+    OMP_FOR
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int q = y * nx + x;
@@ -361,6 +391,7 @@ static void stage_diffusion(pfo_ctx *c) {
     capillary(&c->p, S, &ST);
     for (int k = 0; k < 3; ++k) {
         const double *f = c->mu + (size_t)k * n;
+        OMP_FOR
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 int q = y * nx + x;
@@ -370,6 +401,7 @@ static void stage_diffusion(pfo_ctx *c) {
     }
     for (int i = 0; i < c->p.n_h; ++i) {
         const double *ci = c->C + (size_t)i * n, *mi = c->mu + (size_t)i * n;
+        OMP_FOR
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 int q = y * nx + x;
@@ -417,6 +449,7 @@ static void surface_force(const pfo_ctx *c, int q, double *fx, double *fy) {
  * then the CD gradient of p (ghost p mirrors the wall rows). */
 static void stage_hydro(pfo_ctx *c) {
     int nx = c->nx, ny = c->ny, n = c->n;
+    OMP_FOR
     for (int q = 0; q < n; ++q) {
         double fx, fy;
         surface_force(c, q, &fx, &fy);
@@ -437,6 +470,7 @@ static void stage_hydro(pfo_ctx *c) {
         c->u[n + q] = uy;
         c->pr[q] = s + 0.5 * CS2 * (ux * c->gradrho[q] + uy * c->gradrho[n + q]);
     }
+    OMP_FOR
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int q = y * nx + x;
@@ -461,6 +495,7 @@ static double gbar_eq(const node_macro *m, int a) {
 static void stage_collide(pfo_ctx *c) {
     int nx = c->nx, ny = c->ny, n = c->n, nh = c->p.n_h;
     const pfo_params *P = &c->p;
+    OMP_FOR
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int q = y * nx + x;
@@ -576,6 +611,7 @@ static void stage_collide(pfo_ctx *c) {
  * receiving-node half of the diffusion term (R12). */
 static void stage_stream(pfo_ctx *c) {
     int nx = c->nx, ny = c->ny, n = c->n, nh = c->p.n_h;
+    OMP_FOR
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int q = y * nx + x;

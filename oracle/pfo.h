@@ -61,6 +61,10 @@ double pfo_bulk_energy(const pfo_params *p, double c1, double c2, double c3);
 void pfo_chem_potential(const pfo_params *p, const double c[3], const double lap[3], double mu[3]);
 double pfo_mixture_tau(const pfo_params *p, const double c[3], double gdot);
 
+/* Threads of the per-node loops (OpenMP build); results do not depend on it. */
+void pfo_set_threads(int n);
+int pfo_get_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,7 +59,8 @@ def lib():
     if _lib is None:
         so = os.path.join(_HERE, "libpfo.so")
         src = os.path.join(_HERE, "pfo.c")
-        if not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src):
+        stamp = max(os.path.getmtime(src), os.path.getmtime(os.path.join(_HERE, "build.py")))
+        if not os.path.exists(so) or os.path.getmtime(so) < stamp:
             _build.build()
         L = ct.CDLL(so)
         P = ct.POINTER
@@ -85,8 +86,21 @@ def lib():
         L.pfo_chem_potential.restype = None
         L.pfo_mixture_tau.argtypes = [P(Params), dp, ct.c_double]
         L.pfo_mixture_tau.restype = ct.c_double
+        L.pfo_set_threads.argtypes = [ct.c_int]
+        L.pfo_set_threads.restype = None
+        L.pfo_get_threads.argtypes = []
+        L.pfo_get_threads.restype = ct.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's per-node loops (results do not depend on it)."""
+    lib().pfo_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().pfo_get_threads())
 
 
 def _ptr(a):
