@@ -99,3 +99,23 @@ def test_three_component_with_absent_second_phase_matches_two_phase():
     assert rel_l2(m2["phi"][0], m1["phi"][0]) < 1e-13
     g, h, tau = o2.populations()
     assert np.abs(h[1]).max() < 1e-15
+
+
+def test_thread_count_does_not_change_results():
+    """The per-node loops are split over threads; every node is computed by
+    one thread with the same operations, so 1 and 4 threads agree bit for bit."""
+    from oracle.pfo import set_threads, get_threads
+    case = inputs.rising_bubble_small()
+    keep = get_threads()
+    out = []
+    try:
+        for th in (1, 4):
+            set_threads(th)
+            o = Oracle(case["params"])
+            o.init_fields(case["C"], case["u"], case["p"])
+            o.step(5)
+            out.append(o.macroscopic())
+    finally:
+        set_threads(keep)
+    for k in ("u", "p", "phi", "rho"):
+        assert np.array_equal(out[0][k], out[1][k]), k
