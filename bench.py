@@ -189,7 +189,7 @@ def main():
         "config": {
             "workload": f"{case['name']}: {a.nx}x{a.ny} single domain, {a.bubbles} seeded bubbles R 25-40, "
                         f"power-law liquid n=0.6 K=0.1, density ratio 1000, float32 arithmetic, "
-                        f"state gbar float32 + C float64 + tau float32 (tau_h = 1/2)",
+                        f"state: gbar level float64 + 8 deviations float32, C float64, tau float32 (tau_h = 1/2)",
             "nx": a.nx, "ny": a.ny, "cells": cells, "bytes_per_update": bpu, "kernel_variant": variant,
             "autotune_ms_per_step": tuning, "wall_s_timed": round(wall, 4), "gas_mass": diag[0],
         },

@@ -72,7 +72,7 @@ __device__ __forceinline__ void node_macro(const CaseDev& cd, int par, int x, in
     const long long off = (long long)y * cd.pitch + x;
     float d[9];
     load_devs(cd, par, off, d);
-    const float s = cd.S[par][off];
+    const float s = (float)(cd.P[par][off] + pref_d(cd, y));
     const float jx = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
     const float jy = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
     const float mu13 = n.mu[0] - n.mu[2], mu23 = n.mu[1] - n.mu[2];
@@ -99,15 +99,16 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const CaseDev* __restrict_
     };
     const NodeStencil st = stencil_at(cd, x, y, getc);
     const float ux = uin ? (float)uin[q] : 0.0f, uy = uin ? (float)uin[n + q] : 0.0f;
-    const float p = pin ? (float)pin[q] : 0.0f;
+    const double p = pin ? pin[q] : 0.0;
     float gpx = 0.f, gpy = 0.f;
     if (pin) {
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            const float pp = (float)pin[(long long)mirror_y(y + Lat::ey[a], ny) * nx + wrap_x(x + Lat::ex[a], nx)];
-            const float pm = (float)pin[(long long)mirror_y(y - Lat::ey[a], ny) * nx + wrap_x(x - Lat::ex[a], nx)];
-            gpx += Lat::w[a] * Lat::ex[a] * (pp - pm);
-            gpy += Lat::w[a] * Lat::ey[a] * (pp - pm);
+            const double pp = pin[(long long)mirror_y(y + Lat::ey[a], ny) * nx + wrap_x(x + Lat::ex[a], nx)];
+            const double pm = pin[(long long)mirror_y(y - Lat::ey[a], ny) * nx + wrap_x(x - Lat::ex[a], nx)];
+            const float dp = (float)(pp - pm);
+            gpx += Lat::w[a] * Lat::ex[a] * dp;
+            gpy += Lat::w[a] * Lat::ey[a] * dp;
         }
         gpx *= 1.5f;
         gpy *= 1.5f;
@@ -120,8 +121,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const CaseDev* __restrict_
     const float ps = 0.5f * kCs2 * ugr;                      // p - sum gbar_eq
     const float rc2 = rho * kCs2;
     const long long off = (long long)y * cd.pitch + x;
-    float* S = cd.S[par];
-    S[off] = p - ps;
+    cd.P[par][off] = p - (double)ps - pref_d(cd, y);
     float A[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void export_kernel(const CaseDev* __restric
     if (q >= (long long)nx * ny) return;
     const int y = (int)(q / nx), x = (int)(q - (long long)y * nx);
     const long long n = (long long)nx * ny, off = (long long)y * cd.pitch + x;
-    const float s = cd.S[par][off];
+    const float s = (float)(cd.P[par][off] + pref_d(cd, y));
     float d0 = 0.f, dd[9];
     load_devs(cd, par, off, dd);
     for (int a = 1; a < 9; ++a) {

@@ -28,7 +28,8 @@ constexpr float kCs2 = 1.0f / 3.0f;
 
 // Per-case block in device memory.  State planes are row-major (ny, pitch);
 // `plane` is the element stride between planes.  The gbar state is kept as
-// s = sum_a gbar_a in plane 0 and the deviations d_a = gbar_a - w_a s
+// s = sum_a gbar_a in plane 0 (less the reference p_ref below) and the
+// deviations d_a = gbar_a - w_a s
 // (a = 1..8) in planes 1..8 (float32; the float16 form is described below);
 // d_0 = -sum_{a>0} d_a.  The phase
 // fields C_i are accumulated in float64 planes: their per-step change is far
@@ -37,7 +38,8 @@ constexpr float kCs2 = 1.0f / 3.0f;
 struct CaseDev {
     int nx, ny, pitch, n_h;
     long long plane;
-    float* S[2];        // 9 planes each (ping-pong)
+    double* P[2];       // s - p_ref (float64), one plane each (ping-pong)
+    float* S[2];        // d_a in plane a-1 (a = 1..8), or j_x, j_y in planes 0, 1 of the float16 form
     double* C[2];       // n_h planes each (float64)
     float* T[2];        // tau of the previous step
     float* H[2];        // stored-hbar form: q_a = hbar_a - w_a C_i, 9*n_h planes each, else null
@@ -58,7 +60,19 @@ struct CaseDev {
     // float64 coefficients of the bulk chemical potential; dA_j = 4 Sigma_T / (xi Sigma_j)
     double dsig12, dsig13, dsig23, dlam, dSig[3], dA[3];
     double drho[3];     // component densities in float64
+    // The state keeps s' = s - p_ref(y) with p_ref(y) = pref_g (pref_yc - y),
+    // the hydrostatic pressure of the liquid (pref_g = rho_3 g, pref_yc the
+    // mid-height): in a tall domain under gravity s reaches rho g H / 2, and
+    // float32 spacing at that size is comparable to the gas momentum at
+    // density ratio 1000.  The reference is exact bookkeeping: every use adds
+    // it back or takes its exact differences.
+    float pref_g, pref_yc;
 };
+
+__device__ __forceinline__ float pref(const CaseDev& cd, int y) { return cd.pref_g * (cd.pref_yc - (float)y); }
+__device__ __forceinline__ double pref_d(const CaseDev& cd, int y) {
+    return (double)cd.pref_g * ((double)cd.pref_yc - (double)y);
+}
 
 struct TileDev {
     int case_id, x0, y0, pad;
@@ -87,7 +101,8 @@ __device__ __forceinline__ int mirror_y(int y, int ny) {
     return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
 }
 
-// Float16 storage form.  The momentum j = sum_a e_a d_a stays float32 (it is
+// Float16 storage form.  s stays float64 (plane P) and the momentum
+// j = sum_a e_a d_a float32 (it is
 // conserved by the collision, so rounding it would persist, and at density
 // ratio 1000 it is a small difference of the deviations); the rest of the
 // deviations is kept as six pair moments in float16,
@@ -97,7 +112,7 @@ __device__ __forceinline__ int mirror_y(int y, int ny) {
 // normal, and the scaling is exact.
 constexpr float kQScale = 16384.0f;
 constexpr int kQPlanes = 6;    // float16 planes
-constexpr int kSPlanes16 = 3;  // float32 planes: s, j_x, j_y
+constexpr int kSPlanes16 = 2;  // float32 planes: j_x, j_y
 
 __device__ __forceinline__ void pack_devs(const float d[9], float& jx, float& jy, float m[6]) {
     const float x5 = d[5] - d[7], x6 = d[6] - d[8];
@@ -128,20 +143,20 @@ __device__ __forceinline__ void load_devs(const CaseDev& cd, int par, long long 
     if (cd.Q[par]) {
         float m[6];
         for (int k = 0; k < kQPlanes; ++k) m[k] = (float)cd.Q[par][k * cd.plane + off] * cd.qinv;
-        unpack_devs(cd.S[par][cd.plane + off], cd.S[par][2 * cd.plane + off], m, d);
+        unpack_devs(cd.S[par][off], cd.S[par][cd.plane + off], m, d);
     } else {
-        for (int a = 1; a < 9; ++a) d[a] = cd.S[par][a * cd.plane + off];
+        for (int a = 1; a < 9; ++a) d[a] = cd.S[par][(a - 1) * cd.plane + off];
     }
 }
 __device__ __forceinline__ void store_devs(const CaseDev& cd, int par, long long off, const float d[9]) {
     if (cd.Q[par]) {
         float jx, jy, m[6];
         pack_devs(d, jx, jy, m);
-        cd.S[par][cd.plane + off] = jx;
-        cd.S[par][2 * cd.plane + off] = jy;
+        cd.S[par][off] = jx;
+        cd.S[par][cd.plane + off] = jy;
         for (int k = 0; k < kQPlanes; ++k) cd.Q[par][k * cd.plane + off] = (_Float16)(m[k] * cd.qscale);
     } else {
-        for (int a = 1; a < 9; ++a) cd.S[par][a * cd.plane + off] = d[a];
+        for (int a = 1; a < 9; ++a) cd.S[par][(a - 1) * cd.plane + off] = d[a];
     }
 }
 

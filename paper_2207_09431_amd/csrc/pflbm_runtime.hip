@@ -23,7 +23,7 @@ constexpr int kReduceMax = 1024;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct CaseLayout {
-    size_t S[2], C[2], T[2], H[2], Q[2];   // byte offsets into the workspace
+    size_t P[2], S[2], C[2], T[2], H[2], Q[2];   // byte offsets into the workspace; P[b] starts buffer b
     int pitch;
     long long plane;                 // elements per plane
 };
@@ -129,7 +129,8 @@ bool make_layout(const pflbm_params* cases, int n, Layout* L) {
         const size_t pb = sizeof(float) * (size_t)cl.plane;
         const bool f16 = p.storage == 1;
         for (int b = 0; b < 2; ++b) {
-            cl.S[b] = off; off = align_up(off + (f16 ? kSPlanes16 : 9) * pb, kAlign);
+            cl.P[b] = off; off = align_up(off + 2 * pb, kAlign);                      // float64
+            cl.S[b] = off; off = align_up(off + (f16 ? kSPlanes16 : 8) * pb, kAlign);
             if (f16) { cl.Q[b] = off; off = align_up(off + kQPlanes * (pb / 2), kAlign); }
             else cl.Q[b] = 0;
             cl.C[b] = off; off = align_up(off + (size_t)p.n_h * 2 * pb, kAlign);   // float64
@@ -232,6 +233,7 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
         memset(&d, 0, sizeof(d));
         d.nx = p.nx; d.ny = p.ny; d.pitch = cl.pitch; d.n_h = p.n_h; d.plane = cl.plane;
         for (int b = 0; b < 2; ++b) {
+            d.P[b] = reinterpret_cast<double*>(c->ws + cl.P[b]);
             d.S[b] = reinterpret_cast<float*>(c->ws + cl.S[b]);
             d.C[b] = reinterpret_cast<double*>(c->ws + cl.C[b]);
             d.T[b] = reinterpret_cast<float*>(c->ws + cl.T[b]);
@@ -253,6 +255,8 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
         d.mob[1] = (float)(p.D0 / S[1]);
         d.omh = (float)(1.0 / (p.tau_h + 0.5));
         d.g = (float)p.g; d.fx = (float)p.fx;
+        d.pref_g = (float)(p.rho[2] * p.g);
+        d.pref_yc = (float)(0.5 * (p.ny - 1));
         d.dsig12 = p.sigma12; d.dsig13 = p.sigma13; d.dsig23 = p.sigma23; d.dlam = p.Lambda;
         for (int j = 0; j < 3; ++j) { d.dSig[j] = S[j]; d.dA[j] = 4.0 * ST / (p.xi * S[j]); }
     }
@@ -423,7 +427,7 @@ int32_t pflbm_bubble_centroid_velocity(pflbm_ctx* c, int32_t k, int32_t comp, do
 size_t pflbm_state_bytes(const pflbm_ctx* c) {
     if (!c) return 0;
     size_t b = 0;
-    for (size_t k = 0; k < c->prm.size(); ++k) b += c->L.cl[k].S[1] - c->L.cl[k].S[0];
+    for (size_t k = 0; k < c->prm.size(); ++k) b += c->L.cl[k].P[1] - c->L.cl[k].P[0];
     return b;
 }
 
@@ -431,8 +435,8 @@ static int32_t copy_state(pflbm_ctx* c, char* dst, const char* src, bool to_ws) 
     size_t o = 0;
     for (size_t k = 0; k < c->prm.size(); ++k) {
         const CaseLayout& cl = c->L.cl[k];
-        const size_t len = cl.S[1] - cl.S[0];
-        char* w = c->ws + cl.S[c->par];
+        const size_t len = cl.P[1] - cl.P[0];
+        char* w = c->ws + cl.P[c->par];
         hipError_t e = to_ws ? hipMemcpyAsync(w, src + o, len, hipMemcpyDeviceToDevice, c->stream)
                              : hipMemcpyAsync(dst + o, w, len, hipMemcpyDeviceToDevice, c->stream);
         if (e != hipSuccess) return PFLBM_ERR_DEVICE;
@@ -482,9 +486,10 @@ void* pflbm_stream(const pflbm_ctx* c) { return c ? (void*)c->stream : nullptr; 
 double pflbm_bytes_per_update(const pflbm_ctx* c) {
     if (!c) return 0.0;
     const pflbm_params& p = c->prm[0];
-    // gbar: s + 8 deviations (float32), or s, j_x, j_y (float32) + 6 pair
-    // moments (float16); C_i (float64); tau (float32); hbar (float32) when stored
-    double b = (p.storage == 1 ? 3 * 4 + 6 * 2 : 9 * 4) + 8.0 * p.n_h + 4;
+    // gbar: s (float64) + 8 deviations (float32), or s (float64) + j_x, j_y
+    // (float32) + 6 pair moments (float16); C_i (float64); tau (float32);
+    // hbar deviations (float32) when stored
+    double b = 8 + (p.storage == 1 ? 2 * 4 + 6 * 2 : 8 * 4) + 8.0 * p.n_h + 4;
     if (p.store_h) b += 9 * 4.0 * p.n_h;
     return 2.0 * b;                        // read once and written once
 }

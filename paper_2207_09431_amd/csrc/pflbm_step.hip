@@ -36,6 +36,16 @@ __device__ __forceinline__ void cd_grad(const float* f, int i, float& gx, float&
     gx = (1.0f / 3.0f) * d1 + (1.0f / 12.0f) * (d5 - d6);
     gy = (1.0f / 3.0f) * d2 + (1.0f / 12.0f) * (d5 + d6);
 }
+// The Laplacian of the float64 phase field, rounded once: it sets the
+// gradient part of mu, which inside a bubble (C = 1 - O(1e-5)) is as small as
+// the bulk part, and the float32 copy's spacing there would be a 1 % error.
+template <int W>
+__device__ __forceinline__ float cd_lap_d(const double* f, int i) {
+    const double c = f[i];
+    const double s1 = (f[i + 1] - c) + (f[i - 1] - c), s2 = (f[i + W] - c) + (f[i - W] - c);
+    const double s5 = (f[i + W + 1] - c) + (f[i - W - 1] - c), s6 = (f[i + W - 1] - c) + (f[i - W + 1] - c);
+    return (float)((2.0 / 3.0) * (s1 + s2) + (1.0 / 6.0) * (s5 + s6));
+}
 template <int W>
 __device__ __forceinline__ float cd_lap(const float* f, int i) {
     const float c = f[i];
@@ -101,7 +111,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     __shared__ float sMu[NMU][N2];
     __shared__ float sUx[N2], sUy[N2], sP[N2];
     __shared__ float sD[9][N1];      // post-collision deviations d*_a
-    __shared__ float sS[N1];         // s = sum gbar at the source
+    __shared__ double sS[N1];        // s - p_ref at the source (float64)
     // post-collision hbar: without the (1-omega_h) hbar part when hbar is
     // stored, else as its deviation from w_a C at the source
     __shared__ float sH[NH][9][N1];
@@ -119,9 +129,11 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     const int nx = cd.nx, ny = cd.ny, pitch = cd.pitch;
     const long long plane = cd.plane;
     const int x0 = tile.x0, y0 = tile.y0;
+    const double* Pin = cd.P[par];
     const float* Sin = cd.S[par];
     const double* Cin = cd.C[par];
     const float* Tin = cd.T[par];
+    double* Pout = cd.P[par ^ 1];
     float* Sout = cd.S[par ^ 1];
     double* Cout = cd.C[par ^ 1];
     float* Tout = cd.T[par ^ 1];
@@ -141,7 +153,8 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     constexpr int KA = (N3 + NT - 1) / NT, KB = (N2 + NT - 1) / NT;
     constexpr int ND = F16 ? 2 + kQPlanes : 8;
     double ca[KA][NH];
-    float ps[KB], pd[KB][ND], pt[KB];
+    double ps[KB];
+    float pd[KB][ND], pt[KB];
     // Element offset of region node (rx, ry) of the region with halo h: tiles
     // whose regions stay clear of the walls and of the periodic seam take the
     // plain offset, the others wrap x and mirror y.
@@ -166,15 +179,15 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             const int idx = min(tid + k * NT, N2 - 1);
             const int ry = idx / W2, rx = idx - ry * W2;
             const uint32_t eo = node(rx, ry, 2);
-            ps[k] = gld(Sin, eo * 4u);
+            ps[k] = gld(Pin, eo * 8u);
             if (F16) {
-                pd[k][0] = gld(Sin + plane, eo * 4u);
-                pd[k][1] = gld(Sin + 2 * plane, eo * 4u);
+                pd[k][0] = gld(Sin, eo * 4u);
+                pd[k][1] = gld(Sin + plane, eo * 4u);
 #pragma unroll
                 for (int q = 0; q < kQPlanes; ++q) pd[k][2 + q] = (float)gld(Qin + q * plane, eo * 2u);
             } else {
 #pragma unroll
-                for (int a = 1; a < 9; ++a) pd[k][a - 1] = gld(Sin + a * plane, eo * 4u);
+                for (int a = 1; a < 9; ++a) pd[k][a - 1] = gld(Sin + (a - 1) * plane, eo * 4u);
             }
             pt[k] = gld(Tin, eo * 4u);
         }
@@ -208,7 +221,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
             cd_grad<W3>(sC[i], i3, gcx[i], gcy[i]);
-            lc[i] = cd_lap<W3>(sC[i], i3);
+            lc[i] = cd_lap_d<W3>(sCd[i], i3);
         }
         float mu[3];
         chem_potential<NH>(cd, sCd[0][i3], NH == 2 ? sCd[NH - 1][i3] : 0.0, lc[0], lc[1], mu);
@@ -216,7 +229,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         if (NH == 2) sMu[1][idx] = mu[1];
         sMu[NH][idx] = mu[2];
         if (gyr >= 0 && gyr < ny) {
-            const float s = ps[k];
+            const double s = ps[k];
             float jx, jy;
             float d[9];
             if (F16) {
@@ -271,7 +284,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
                     sH[0][7][i1] = gcy[1];
                 }
             }
-            sP[idx] = s + 0.5f * kCs2 * (ux * grx + uy * gry);
+            sP[idx] = (float)s + 0.5f * kCs2 * (ux * grx + uy * gry);
         }
     }
     __syncthreads();
@@ -282,8 +295,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             const int ry = idx / W2, rx = idx - ry * W2;
             const int gyr = y0 - 2 + ry;
             if ((gyr < 0 && gyr >= -2) || (gyr >= ny && gyr < ny + 2)) {
-                const int rm = mirror_y(gyr, ny) - (y0 - 2);
-                sP[idx] = sP[rm * W2 + rx];
+                // p mirrors; sP holds p - p_ref, so the reference's difference is added
+                const int ym = mirror_y(gyr, ny);
+                sP[idx] = sP[(ym - (y0 - 2)) * W2 + rx] + cd.pref_g * (float)(gyr - ym);
             }
         }
         __syncthreads();
@@ -300,7 +314,6 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         float d[9];
 #pragma unroll
         for (int a = 1; a < 9; ++a) d[a] = sD[a][idx];
-        const float s = sS[idx];
         d[0] = -(d[1] + d[2] + d[3] + d[4] + d[5] + d[6] + d[7] + d[8]);
         const float tprev = sDif[0][idx];
 
@@ -321,6 +334,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const float rho = sR[i3];
         float gpx, gpy;
         cd_grad<W2>(sP, i2, gpx, gpy);
+        gpy -= cd.pref_g;   // sP holds p - p_ref, and grad p_ref = (0, -rho_3 g) exactly
         const float mu1 = sMu[0][i2], mu3 = sMu[NH][i2];
         const float mu2 = NH == 2 ? sMu[1][i2] : 0.0f;
         const float ux = sUx[i2], uy = sUy[i2];
@@ -481,7 +495,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             const int i1 = (oy + 1) * W1 + ox + 1;
             const int i2 = (oy + 2) * W2 + ox + 2;
             const uint32_t eo = (uint32_t)(gyr * pitch + gx);
-            float sv[9], dv[9];
+            float dv[9];
             int src[9], dir[9];
             bool bb[9];
 #pragma unroll
@@ -492,32 +506,38 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
                 dir[a] = bb[a] ? Lat::opp[a] : a;
             }
             // s(y) = sum_a w_a s(z_a) + sum_a d*_a(z_a), formed around the node's
-            // own s with sum_a w_a = 1 taken exactly (the float32 weights sum to
-            // 1 + 8e-9, which would inflate the pressure level every step)
-            const float sy0 = sS[i1];
-            float ssum = 0.f, dsum = 0.f;
+            // own s.  The stored s' = s - p_ref: a source one row below carries
+            // p_ref(z) - p_ref(y) = rho_3 g e_y exactly (zero for a bounced one)
+            const double sy0 = sS[i1];
+            const double pg = cd.pref_g;
+            double ssum = 0.0;
+            float dsum = 0.f;
+            double sv[9];
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 sv[a] = sS[src[a]];
+                if (!bb[a] && Lat::ey[a] != 0) sv[a] += Lat::ey[a] > 0 ? pg : -pg;
                 dv[a] = sD[dir[a]][src[a]];
-                if (a > 0 && !bb[a]) ssum += Lat::w[a] * (sv[a] - sy0);
+                if (a > 0 && !bb[a]) ssum += (double)Lat::w[a] * (sv[a] - sy0);
                 dsum += dv[a];
             }
-            const float snew = sy0 + (ssum + dsum);
-            gst(Sout, eo * 4u, snew);
-            if (F16) {
-                float da[9], jx, jy, m[kQPlanes];
+            const double snew = sy0 + (ssum + (double)dsum);
+            gst(Pout, eo * 8u, snew);
+            // d_a(y) = w_a (s(z_a) - s(y)) + d*_a(z_a), the level difference taken in float64
+            float da[9];
 #pragma unroll
-                for (int a = 1; a < 9; ++a) da[a] = Lat::w[a] * (sv[a] - snew) + dv[a];
+            for (int a = 1; a < 9; ++a) da[a] = Lat::w[a] * (float)(sv[a] - snew) + dv[a];
+            if (F16) {
+                float jx, jy, m[kQPlanes];
                 pack_devs(da, jx, jy, m);
-                gst(Sout + plane, eo * 4u, jx);
-                gst(Sout + 2 * plane, eo * 4u, jy);
+                gst(Sout, eo * 4u, jx);
+                gst(Sout + plane, eo * 4u, jy);
 #pragma unroll
                 for (int k = 0; k < kQPlanes; ++k)
                     gst(Qout + k * plane, eo * 2u, (_Float16)(m[k] * qscale));   // nearest even
             } else {
 #pragma unroll
-                for (int a = 1; a < 9; ++a) gst(Sout + a * plane, eo * 4u, Lat::w[a] * (sv[a] - snew) + dv[a]);
+                for (int a = 1; a < 9; ++a) gst(Sout + (a - 1) * plane, eo * 4u, da[a]);
             }
 
             // region index of the output node and of each source on R3 (for C)

@@ -47,7 +47,7 @@ def test_bytes_per_update(torch):
     case = inputs.rising_bubble_small()
     s16, _ = gpu_run(case, 0, storage=1)
     s32, _ = gpu_run(case, 0)
-    assert s16.bytes_per_update() == 72.0 and s32.bytes_per_update() == 96.0
+    assert s16.bytes_per_update() == 80.0 and s32.bytes_per_update() == 104.0
     assert s16.state_bytes() < s32.state_bytes()
 
 
@@ -79,7 +79,7 @@ def test_powerlaw_bubble_float16(torch):
 def test_three_component_float16(torch):
     case = inputs.three_component(nx=96, ny=192)
     s, m = gpu_run(case, 100, storage=1)
-    assert s.bytes_per_update() == 88.0
+    assert s.bytes_per_update() == 96.0
     ru, rc = errors(m, run_case(case, 100).macroscopic())
     assert ru <= TOL16 and rc <= TOL16
 

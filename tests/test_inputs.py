@@ -47,3 +47,20 @@ def test_place_bubbles_constraints():
         for (x2, y2, r2) in b[:i]:
             dx = (x - x2) - 512 * round((x - x2) / 512)
             assert dx * dx + (y - y2) ** 2 >= (r + r2 + 8.0) ** 2
+
+
+def test_rest_pressure_hydrostatic_and_laplace():
+    nx, ny, xi, sigma, rho_l, g = 200, 300, 4.0, 1e-4, 1.0, 2e-7
+    bubbles = [(60.0, 100.0, 25.0), (150.0, 220.0, 30.0)]
+    p = inputs.rest_pressure(nx, ny, bubbles, xi, sigma, rho_l, g)
+    yc = 0.5 * (ny - 1)
+    # far from every bubble: the liquid's hydrostatic profile, exactly
+    for (x, y) in [(5, 10), (190, 20), (110, 150), (20, 290)]:
+        assert p[y, x] == rho_l * g * (yc - y)
+    # at a centre: the liquid pressure at that height plus sigma / R
+    for (cx, cy, r) in bubbles:
+        want = rho_l * g * (yc - cy) + sigma / r
+        assert abs(p[int(cy), int(cx)] - want) < 1e-6 * sigma / r
+    # inside a bubble the pressure carries no hydrostatic gradient
+    cx, cy, r = bubbles[0]
+    assert abs(p[int(cy) + 10, int(cx)] - p[int(cy) - 10, int(cx)]) < 1e-4 * sigma / r
