@@ -122,6 +122,9 @@ def batch_forms(torch, Solver, inputs, steps, warmup):
         b.init_fields(k, c["C"], c["u"], c["p"])
     bvar = b.autotune(steps=3)
     ms_b, _ = timed_steps(torch, [b], steps, warmup)
+    b.set_graph(10)                                # the same launches replayed from a hipGraph
+    ms_g, _ = timed_steps(torch, [b], steps - steps % 10, 10)
+    b.set_graph(0)
     singles = []
     for c in cases:
         s = Solver(c["params"])
@@ -131,6 +134,7 @@ def batch_forms(torch, Solver, inputs, steps, warmup):
     ms_s, _ = timed_steps(torch, singles, steps, warmup)
     return {"cases": len(cases), "cells": cells, "variant": bvar,
             "batched_mlups": round(cells / (ms_b * 1e-3) / 1e6, 1),
+            "batched_graph_mlups": round(cells / (ms_g * 1e-3) / 1e6, 1),
             "one_by_one_mlups": round(cells / (ms_s * 1e-3) / 1e6, 1),
             "batched_ms_per_step": round(ms_b, 4), "one_by_one_ms_per_step": round(ms_s, 4)}
 

@@ -243,7 +243,9 @@ __device__ __forceinline__ float powerlaw_nu(const CaseDev& cd, float gdot) {
         if (cd.nexp > 1.0f) return cd.numin;
         nu = cd.K;
     } else {
-        nu = cd.K * exp2f((cd.nexp - 1.0f) * log2f(gdot));
+        // hardware log2/exp2: gdot > 0 here, and for a denormal gdot (< 1e-38)
+        // the clamp below decides the result anyway
+        nu = cd.K * __builtin_amdgcn_exp2f((cd.nexp - 1.0f) * __builtin_amdgcn_logf(gdot));
     }
     return fminf(fmaxf(nu, cd.numin), cd.numax);
 }
