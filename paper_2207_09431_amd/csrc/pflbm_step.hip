@@ -510,23 +510,24 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             // p_ref(z) - p_ref(y) = rho_3 g e_y exactly (zero for a bounced one)
             const double sy0 = sS[i1];
             const double pg = cd.pref_g;
-            double ssum = 0.0;
-            float dsum = 0.f;
-            double sv[9];
+            // level differences to the sources, exact in float64 and then small
+            // enough for float32: ds_a = s(z_a) - s(y) (with the reference's)
+            float ds[9], ssum = 0.f, dsum = 0.f;
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
-                sv[a] = sS[src[a]];
-                if (!bb[a] && Lat::ey[a] != 0) sv[a] += Lat::ey[a] > 0 ? pg : -pg;
+                double sv = sS[src[a]] - sy0;
+                if (!bb[a] && Lat::ey[a] != 0) sv += Lat::ey[a] > 0 ? pg : -pg;
+                ds[a] = (float)sv;
                 dv[a] = sD[dir[a]][src[a]];
-                if (a > 0 && !bb[a]) ssum += (double)Lat::w[a] * (sv[a] - sy0);
+                if (a > 0 && !bb[a]) ssum += Lat::w[a] * ds[a];
                 dsum += dv[a];
             }
-            const double snew = sy0 + (ssum + (double)dsum);
-            gst(Pout, eo * 8u, snew);
-            // d_a(y) = w_a (s(z_a) - s(y)) + d*_a(z_a), the level difference taken in float64
+            const float dnew = ssum + dsum;               // s(t+1) - s(y)
+            gst(Pout, eo * 8u, sy0 + (double)dnew);
+            // d_a(y) = w_a (s(z_a) - s(t+1)) + d*_a(z_a)
             float da[9];
 #pragma unroll
-            for (int a = 1; a < 9; ++a) da[a] = Lat::w[a] * (float)(sv[a] - snew) + dv[a];
+            for (int a = 1; a < 9; ++a) da[a] = Lat::w[a] * (ds[a] - dnew) + dv[a];
             if (F16) {
                 float jx, jy, m[kQPlanes];
                 pack_devs(da, jx, jy, m);
