@@ -66,20 +66,22 @@ typedef struct {
     double tau_h;              /* relaxation time of hbar (0.5 in the paper) */
     double g;                  /* gravity: F_b = rho (fx, -g) (Eq. (12)) */
     double fx;                 /* horizontal body acceleration (0 in the paper's bubble runs) */
-    int32_t storage;           /* 0: gbar deviations in float32; 1: in float16 (see below) */
+    int32_t storage;           /* 0: gbar deviations in float32; 1: float16 pair moments (see below) */
     int32_t store_h;           /* 0: keep only C_i when tau_h = 0.5 (exact), 1: store hbar */
 } pflbm_params;
 
 /*
- * State forms.  gbar is kept as s = sum_a gbar_a (float32) and the deviations
- * from the rest-state weights d_a = gbar_a - w_a s, a = 1..8 (d_0 follows
- * from sum_a d_a = 0); C_i is kept in float64 and tau in float32.
- *  - storage = 0: d_a in float32 (96 B moved per lattice update, two-phase).
- *  - storage = 1: s and the momentum j = sum_a e_a d_a in float32, and the
- *    six pair moments (d1+d3, d2+d4, d5+d7, d6+d8, d5-d7, d6-d8) * 2^14
- *    rounded to float16 (nearest even): 72 B per update; the arithmetic
- *    stays float32.  Float16 rounding then reaches only moments that the
- *    collision relaxes.  Requires store_h = 0.
+ * State forms.  gbar is kept as its level s = sum_a gbar_a (float64, stored
+ * against the liquid's hydrostatic profile rho_3 g (y_c - y), y_c the
+ * mid-height) and the deviations from the rest-state weights
+ * d_a = gbar_a - w_a s, a = 1..8 (d_0 follows from sum_a d_a = 0); C_i is
+ * kept in float64 and tau in float32.
+ *  - storage = 0: d_a in float32 (104 B moved per lattice update, two-phase).
+ *  - storage = 1: the momentum j = sum_a e_a d_a in float32 and the six pair
+ *    moments (d1+d3, d2+d4, d5+d7, d6+d8, d5-d7, d6-d8) * 2^14 rounded to
+ *    float16 (nearest even): 80 B per update; the arithmetic stays float32.
+ *    Float16 rounding then reaches only moments that the collision relaxes.
+ *    Requires store_h = 0.
  *  - store_h = 0 (requires tau_h = 0.5): hbar relaxes at rate 1, so the
  *    post-collision hbar depends only on time-t fields and keeping C_i alone
  *    is exact.  store_h = 1 keeps hbar as 9 n_h float32 planes of the
@@ -101,7 +103,8 @@ size_t pflbm_workspace_bytes(const pflbm_params* cases, int32_t ncases);
  * (nx or ny < 5, n_h not 1 or 2, rho_k <= 0, nu_k <= 0, nu_min <= 0 or
  * nu_min > nu_max, K <= 0 with a power-law component, xi <= 0, D0 < 0,
  * tau_h <= 0, a Sigma_i <= 0, store_h = 0 with tau_h != 0.5, storage not
- * 0 or 1, nx rounded up to 64 times ny at or above 2^29 nodes); UNSUPPORTED for storage = 1 with store_h = 1; WORKSPACE when the
+ * 0 or 1, nx rounded up to 64 times ny at or above 2^29 nodes);
+ * UNSUPPORTED for storage = 1 with store_h = 1; WORKSPACE when the
  * workspace is NULL, small or misaligned; DEVICE when a HIP call fails.
  */
 int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspace, size_t bytes,
