@@ -85,10 +85,10 @@ def test_three_component_float16(torch):
 
 
 def test_crop_float16(torch):
-    """The 256 x 512 window of the large seeded domain."""
+    """The 256 x 512 window of the large seeded domain, 2,000 steps."""
     case = inputs.many_bubbles_crop()
-    _, m = gpu_run(case, 200, storage=1)
-    ru, rc = errors(m, run_case(case, 200).macroscopic())
+    _, m = gpu_run(case, 2000, storage=1)
+    ru, rc = errors(m, run_case(case, 2000).macroscopic())
     assert ru <= TOL16 and rc <= TOL16
 
 

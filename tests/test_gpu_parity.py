@@ -131,6 +131,14 @@ def test_variable_mobility_short(torch):
     compare(m, o.macroscopic())
 
 
+def test_crop_2000_steps(torch):
+    """The 256 x 512 window of the large seeded domain (density ratio 1000,
+    power-law liquid) after the 2,000 steps of the float32 bound."""
+    case = inputs.many_bubbles_crop()
+    s, m = gpu_run(case, 2000)
+    compare(m, run_case(case, 2000).macroscopic())
+
+
 def test_powerlaw_bubble(torch):
     case = inputs.powerlaw_bubble(n=0.5, nx=100, ny=200, d=50.0)
     s, m = gpu_run(case, 300)
