@@ -16,9 +16,12 @@
 //   D  on the tile: gather the post-collision populations (half-way
 //      bounce-back at the walls), add the receiving-node half of the
 //      diffusion term and write the new state.
-// gbar is carried as s = sum gbar plus deviations d_a = gbar_a - w_a s so that
-// the momentum moment is formed from small numbers (float32 at density
-// ratio 1000).
+// gbar is carried as its level s = sum gbar (float64, against the liquid's
+// hydrostatic profile) plus float32 deviations d_a = gbar_a - w_a s, so that
+// the momentum moment is formed from small numbers (at density ratio 1000
+// the gas momentum is orders of magnitude below the level).  All global loads
+// of a tile are issued in phase A; phase C reads its node's state from LDS,
+// where phase B parks it.
 #include <type_traits>
 
 #include "pflbm_internal.h"
