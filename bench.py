@@ -66,6 +66,26 @@ def measured_traffic(variant, nx, ny):
     return None
 
 
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """GB/s (bytes read + written) of a plain device-to-device copy of `mib`
+    MiB on this GPU: the attainable side of the HBM roofline."""
+    n = mib << 20
+    x = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * n / (ms * 1e-3) / 1e9
+
+
 def timed_steps(torch, solvers, steps, warmup):
     """Milliseconds per step for advancing every solver by one step per step
     (all on the current stream), measured with events on that stream."""
@@ -203,6 +223,9 @@ def main():
     }
     del s
     torch.cuda.empty_cache()
+    copy_gbs = copy_bandwidth(torch)
+    out["roofline"]["measured_copy_GBs"] = round(copy_gbs, 1)
+    out["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
     if not a.no_forms:
         forms = {"batched_48": batch_forms(torch, Solver, inputs, max(20, a.steps // 4), 5)}
         torch.cuda.empty_cache()
