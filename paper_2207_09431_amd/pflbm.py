@@ -144,7 +144,9 @@ class Solver:
         if nbytes == 0:
             raise PflbmError("pflbm_workspace_bytes", -1)
         with torch.cuda.device(self.device):
-            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            # zeroed so that the row padding (never written by the kernels) is
+            # deterministic in checkpoints taken with get_state
+            self.workspace = torch.zeros(nbytes, dtype=torch.uint8, device=self.device)
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ct.c_void_p()
         _check("pflbm_create", L.pflbm_create(arr, len(cases), ct.c_void_p(self.workspace.data_ptr()), nbytes,

@@ -79,3 +79,17 @@ def test_autotune_leaves_state_and_results_unchanged(Solver, tmp_path):
     again = Solver(case["params"])
     again.init_fields(0, case["C"], case["u"], case["p"])
     assert again.autotune(steps=3, cache=str(tmp_path / "tune.json")) == name
+
+
+def test_checkpoints_of_two_runs_are_bitwise_equal(Solver):
+    """get_state copies whole planes, row padding included; the workspace
+    starts zeroed, so two runs from the same inputs give identical bytes."""
+    case = inputs.static_bubble(nx=70, ny=45, radius=12.0)
+    states = []
+    for _ in range(2):
+        s = Solver(dict(case["params"], store_h=1))
+        s.init_fields(0, case["C"], inputs.velocity_noise(70, 45, 3, 1e-3), None)
+        s.step(9)
+        states.append(s.get_state().cpu().numpy())
+        s.close()
+    assert np.array_equal(states[0], states[1])
