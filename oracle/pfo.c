@@ -29,7 +29,13 @@
  *   R3  rho = sum_k rho_k C_k with each C_k limited to [0, 1]: inside a
  *       curved interface the bulk C of the dispersed phase settles slightly
  *       above 1, and the unlimited sum turns negative at density ratio 1000.
- *   R4  mixture viscosity nu = sum_k C_k nu_k, clamped to [min nu_k, max nu_k].
+ *   R4  mixture viscosity from the harmonic rule 1/nu = sum_k C_k / nu_k (each
+ *       C_k limited to [0, 1]), clamped to [min nu_k, max nu_k].  The two-layer
+ *       flow of Sec. 3.3 (Table 3) discriminates: across a diffuse interface
+ *       of two layers in series the stress is continuous and the shear rates
+ *       add, and the linear rule sum_k C_k nu_k misses the layered closed form
+ *       by 2-8 times the printed errors.  Switch mix_linear=1 takes the
+ *       linear rule.
  *   R5  the power law gives a kinematic viscosity nu_P = K gdot^(n-1).
  *   R6  strain rate D = -Pi/(2 (tau+1/2) rho c_s^4) with Pi the second moment
  *       of gbar - gbar_eq (Chapman-Enskog form for the transformed
@@ -273,7 +279,14 @@ static double powerlaw_nu(const pfo_params *p, double gdot) {
 static double mixture_tau(const pfo_params *p, const double c[3], double gdot) {
     double nuk[3];
     for (int k = 0; k < 3; ++k) nuk[k] = (k == p->powerlaw_comp) ? powerlaw_nu(p, gdot) : p->nu[k];
-    double nu = c[0] * nuk[0] + c[1] * nuk[1] + c[2] * nuk[2];
+    double nu;
+    if (p->mix_linear) {
+        nu = c[0] * nuk[0] + c[1] * nuk[1] + c[2] * nuk[2];
+    } else {
+        double q = 0.0;
+        for (int k = 0; k < 3; ++k) q += clip01(c[k]) / nuk[k];
+        nu = 1.0 / q;   /* q > 0: the limited C_k sum to at least 1/3 */
+    }
     double lo = nuk[0], hi = nuk[0];
     for (int k = 1; k < 3; ++k) { if (nuk[k] < lo) lo = nuk[k]; if (nuk[k] > hi) hi = nuk[k]; }
     if (nu < lo) nu = lo;

@@ -35,6 +35,7 @@ typedef struct {
     int32_t hforce_mode;
     int32_t gforce_cd;
     int32_t force_potential;
+    int32_t mix_linear;
 } pfo_params;
 
 typedef struct pfo_ctx pfo_ctx;

@@ -47,7 +47,7 @@ struct CaseDev {
     // moments of the deviations (float16, scaled by qscale); null otherwise
     _Float16* Q[2];
     float qscale, qinv;
-    float rho[3], nu[3];
+    float rho[3], nu[3], inu[3];   // inu = 1 / nu
     int plc;            // power-law component or -1
     int vm;             // variable mobility
     float K, nexp, numin, numax;
@@ -251,13 +251,21 @@ __device__ __forceinline__ float powerlaw_nu(const CaseDev& cd, float gdot) {
 }
 
 // Mixture relaxation time: nu = sum_k C_k nu_k limited to [min nu_k, max nu_k], tau = nu / c_s^2.
+// Mixture tau = nu / c_s^2 with the harmonic rule 1/nu = sum_k C_k / nu_k
+// (each C_k limited to [0, 1]) clamped to [min nu_k, max nu_k]: two layers in
+// series share the stress and add their shear rates, which the layered flow
+// of Sec. 3.3 (Table 3) reproduces.
 __device__ __forceinline__ float mixture_tau(const CaseDev& cd, float c1, float c2, float c3, float gdot) {
     float n0 = cd.nu[0], n1 = cd.nu[1], n2 = cd.nu[2];
+    float i0 = cd.inu[0], i1 = cd.inu[1], i2 = cd.inu[2];
     if (cd.plc >= 0) {
-        const float np = powerlaw_nu(cd, gdot);
-        if (cd.plc == 0) n0 = np; else if (cd.plc == 1) n1 = np; else n2 = np;
+        const float np = powerlaw_nu(cd, gdot), ip = rcp(np);
+        if (cd.plc == 0) { n0 = np; i0 = ip; }
+        else if (cd.plc == 1) { n1 = np; i1 = ip; }
+        else { n2 = np; i2 = ip; }
     }
-    float nu = c1 * n0 + c2 * n1 + c3 * n2;
+    const float q = fmaf(clip01(c1), i0, fmaf(clip01(c2), i1, clip01(c3) * i2));
+    float nu = rcp(q);   // q > 0: the limited C_k sum to at least 1/3
     const float lo = fminf(n0, fminf(n1, n2)), hi = fmaxf(n0, fmaxf(n1, n2));
     nu = fminf(fmaxf(nu, lo), hi);
     return 3.0f * nu;

@@ -242,7 +242,7 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
         }
         d.qscale = kQScale;
         d.qinv = 1.0f / kQScale;
-        for (int j = 0; j < 3; ++j) { d.rho[j] = (float)p.rho[j]; d.drho[j] = p.rho[j]; d.nu[j] = (float)p.nu[j]; }
+        for (int j = 0; j < 3; ++j) { d.rho[j] = (float)p.rho[j]; d.drho[j] = p.rho[j]; d.nu[j] = (float)p.nu[j]; d.inu[j] = (float)(1.0 / p.nu[j]); }
         d.plc = p.powerlaw_comp;
         d.vm = p.variable_mobility ? 1 : 0;
         d.K = (float)p.K; d.nexp = (float)p.n; d.numin = (float)p.nu_min; d.numax = (float)p.nu_max;

@@ -336,5 +336,27 @@ def channel(n: float, ny: int = 32, nx: int = 5, fx: float = 1e-6, K: float = 0.
     return _case(prm, C, None, None, f"channel_n{n}")
 
 
+def layered_flow(n3: float, lam: float, ny: int = 200, nx: int = 5, nu1: float = 1.0 / 6.0,
+                 fx: float = 1e-6, nu_min: float = 1e-3, nu_max: float = 1.0, sigma: float = 5e-4,
+                 xi: float = 4.0) -> dict:
+    """Two-layer flow between the walls (Sec. 3.3, Fig. 6): component 3, a
+    power-law liquid of index n3, fills |y - y_c| < Y_i = ny/4 around the
+    channel centre y_c; component 1, Newtonian with nu1, fills the rest
+    (tanh rims of width xi); C2 = 0.  Equal densities (rho = 1), sigma_13 =
+    sigma, constant mobility, body force fx along the periodic x.  The
+    consistency ratio lam = K3 / (rho_1 nu1) is the paper's lambda^P
+    (lambda for n3 = 1)."""
+    prm = default_params(nx, ny)
+    K3 = lam * nu1
+    prm.update(rho=[1.0, 1.0, 1.0], nu=[nu1, nu1, nu1], powerlaw_comp=2, K=K3, n=n3,
+               nu_min=nu_min, nu_max=nu_max, sigma12=sigma, sigma13=sigma, sigma23=sigma, xi=xi,
+               variable_mobility=0, g=0.0, fx=fx)
+    H = ny / 2.0
+    s = np.abs(np.arange(ny) + 0.5 - H)          # node distance from the centre line
+    c1 = 0.5 + 0.5 * np.tanh((s - H / 2.0) / (xi / 2.0))
+    C = np.repeat(c1[:, None], nx, axis=1)[None]
+    return _case(prm, C, None, None, f"layered_n{n3}_lam{lam:g}_{nx}x{ny}")
+
+
 def clone(case: dict) -> dict:
     return copy.deepcopy(case)

@@ -172,10 +172,12 @@ def test_centroid_velocity(torch):
         assert np.abs(g[4:6] - r[4:6]).max() < 1e-5 * np.abs(r[4:6]).max() + 1e-12
 
 
-def test_rise_velocity_plateau(torch):
-    """Mean rise velocity of the small bubble on its plateau (1,000 and
-    1,500 steps, where it changes by 0.1 %): GPU within 0.5 % of the oracle
-    (the terminal-velocity bound; the measured difference is far smaller)."""
+def test_rise_velocity_matches_oracle(torch):
+    """Mean rise velocity of the small bubble after 1,000 and 1,500 steps:
+    GPU within 1e-4 of the oracle (the paper's terminal-velocity comparison
+    needs 0.5 %; the measured difference is ~2e-7).  The bubble's velocity
+    oscillates by 1-2 % with its shape in this window, so no plateau is
+    asserted."""
     case = inputs.rising_bubble_small()
     s, _ = gpu_run(case, 1000)
     g1 = s.bubble_centroid_velocity(0, 0)[5]
@@ -188,8 +190,8 @@ def test_rise_velocity_plateau(torch):
     o.step(500)
     r2 = o.centroid(0)[5]
     print(f"V_y gpu {g1:.6e} {g2:.6e} oracle {r1:.6e} {r2:.6e} rel {g2 / r2 - 1:.2e}", flush=True)
-    assert abs(r2 - r1) < 5e-3 * abs(r2)          # the oracle is on the plateau
-    assert abs(g1 / r1 - 1) < 5e-3 and abs(g2 / r2 - 1) < 5e-3
+    assert r1 > 0 and r2 > 0                      # the bubble rises
+    assert abs(g1 / r1 - 1) < 1e-4 and abs(g2 / r2 - 1) < 1e-4
 
 
 def test_checkpoint_restart_is_bitwise(torch):
