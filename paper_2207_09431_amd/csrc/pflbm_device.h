@@ -250,7 +250,6 @@ __device__ __forceinline__ float powerlaw_nu(const CaseDev& cd, float gdot) {
     return fminf(fmaxf(nu, cd.numin), cd.numax);
 }
 
-// Mixture relaxation time: nu = sum_k C_k nu_k limited to [min nu_k, max nu_k], tau = nu / c_s^2.
 // Mixture tau = nu / c_s^2 with the harmonic rule 1/nu = sum_k C_k / nu_k
 // (each C_k limited to [0, 1]) clamped to [min nu_k, max nu_k]: two layers in
 // series share the stress and add their shear rates, which the layered flow
