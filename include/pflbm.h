@@ -68,6 +68,10 @@ typedef struct {
     double fx;                 /* horizontal body acceleration (0 in the paper's bubble runs) */
     int32_t storage;           /* 0: gbar deviations in float32; 1: float16 pair moments (see below) */
     int32_t store_h;           /* 0: keep only C_i when tau_h = 0.5 (exact), 1: store hbar */
+    int32_t tau_iterations;    /* 0: tau from the shear rate taken with the previous step's tau
+                                  (the paper's explicit update, Sec. 2.3); m in 1..8: m fixed-point
+                                  passes tau <- tau(gdot(tau)) of the implicit relation Eq. (32),
+                                  started from the previous step's tau */
 } pflbm_params;
 
 /*
@@ -103,7 +107,8 @@ size_t pflbm_workspace_bytes(const pflbm_params* cases, int32_t ncases);
  * (nx or ny < 5, n_h not 1 or 2, rho_k <= 0, nu_k <= 0, nu_min <= 0 or
  * nu_min > nu_max, K <= 0 with a power-law component, xi <= 0, D0 < 0,
  * tau_h <= 0, a Sigma_i <= 0, store_h = 0 with tau_h != 0.5, storage not
- * 0 or 1, nx rounded up to 64 times ny at or above 2^29 nodes);
+ * 0 or 1, tau_iterations outside 0..8, nx rounded up to 64 times ny at or
+ * above 2^29 nodes);
  * UNSUPPORTED for storage = 1 with store_h = 1; WORKSPACE when the
  * workspace is NULL, small or misaligned; DEVICE when a HIP call fails.
  */

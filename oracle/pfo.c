@@ -42,7 +42,8 @@
  *       populations).  Switch strain_literal=1 multiplies Pi by
  *       2tau/(2tau+1) in addition (Eq. (29) fed into Eq. (25) literally).
  *   R7  tau in the strain rate is the cell's tau of the previous step; the
- *       initial tau is the one at zero shear.
+ *       initial tau is the one at zero shear.  tau_iterations = m > 0 adds m
+ *       fixed-point passes of the implicit relation (Eq. (32)) from there.
  *   R8  truncation is a clamp of nu_P to [nu_min, nu_max]; gdot = 0 is taken
  *       explicitly (nu_max if n<1, nu_min if n>1).
  *   R9  stencils: isotropic central differences (CD) for every gradient and
@@ -528,6 +529,9 @@ static void stage_collide(pfo_ctx *c) {
             double gdot = shear_rate(P, Pi, c->tau[q], m.rho);
             double ck[3] = {c->C[q], c->C[n + q], c->C[2 * n + q]};
             double tau = mixture_tau(P, ck, gdot);
+            /* optional fixed-point passes of the implicit relation tau =
+             * tau(gdot(tau)) of Eq. (32), from the previous step's tau */
+            for (int it = 0; it < P->tau_iterations; ++it) tau = mixture_tau(P, ck, shear_rate(P, Pi, tau, m.rho));
             c->taunew[q] = tau;
 
             /* directional derivatives along every e_a and the matching gradients

@@ -36,6 +36,7 @@ typedef struct {
     int32_t gforce_cd;
     int32_t force_potential;
     int32_t mix_linear;
+    int32_t tau_iterations;    /* 0: previous-step tau (R7); m: m fixed-point passes */
 } pfo_params;
 
 typedef struct pfo_ctx pfo_ctx;

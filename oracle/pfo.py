@@ -40,6 +40,7 @@ class Params(ct.Structure):
         ("strain_literal", ct.c_int32), ("mobility_flux", ct.c_int32),
         ("hforce_mode", ct.c_int32), ("gforce_cd", ct.c_int32),
         ("force_potential", ct.c_int32), ("mix_linear", ct.c_int32),
+        ("tau_iterations", ct.c_int32),
     ]
 
 

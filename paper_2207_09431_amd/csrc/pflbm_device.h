@@ -50,6 +50,7 @@ struct CaseDev {
     float rho[3], nu[3], inu[3];   // inu = 1 / nu
     int plc;            // power-law component or -1
     int vm;             // variable mobility
+    int tau_iters;      // fixed-point passes of the implicit tau (0: previous step's tau)
     float K, nexp, numin, numax;
     float sig12, sig13, sig23, lam;
     float Sig[3];

@@ -68,6 +68,7 @@ bool valid_params(const pflbm_params& p) {
     if (p.storage != 0 && p.storage != 1) return false;
     if (p.store_h != 0 && p.store_h != 1) return false;
     if (!p.store_h && p.tau_h != 0.5) return false;
+    if (p.tau_iterations < 0 || p.tau_iterations > 8) return false;
     return true;
 }
 
@@ -245,6 +246,7 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
         for (int j = 0; j < 3; ++j) { d.rho[j] = (float)p.rho[j]; d.drho[j] = p.rho[j]; d.nu[j] = (float)p.nu[j]; d.inu[j] = (float)(1.0 / p.nu[j]); }
         d.plc = p.powerlaw_comp;
         d.vm = p.variable_mobility ? 1 : 0;
+        d.tau_iters = p.tau_iterations;
         d.K = (float)p.K; d.nexp = (float)p.n; d.numin = (float)p.nu_min; d.numax = (float)p.nu_max;
         d.sig12 = (float)p.sigma12; d.sig13 = (float)p.sigma13; d.sig23 = (float)p.sigma23; d.lam = (float)p.Lambda;
         double S[3], ST;

@@ -415,8 +415,12 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const float pxy = ne[5] - ne[6] + ne[7] - ne[8];
         // shear rate: D = -Pi / (2 (tau_prev + 1/2) rho c_s^4), gdot = sqrt(2 D:D)
         const float fs = 4.5f * rcp((tprev + 0.5f) * rho);
-        const float gdot = fs * sqrtf(2.0f * (pxx * pxx + pyy * pyy + 2.0f * pxy * pxy));
-        const float tau = mixture_tau(cd, c[0], c[1], c3, gdot);
+        const float pin = sqrtf(2.0f * (pxx * pxx + pyy * pyy + 2.0f * pxy * pxy));
+        float tau = mixture_tau(cd, c[0], c[1], c3, fs * pin);
+        // optional fixed-point passes of the implicit relation tau = tau(gdot(tau))
+        // (Sec. 2.3, Eq. (32)), started from the previous step's tau
+        for (int it = 0; it < cd.tau_iters; ++it)
+            tau = mixture_tau(cd, c[0], c[1], c3, 4.5f * rcp((tau + 0.5f) * rho) * pin);
         const float om = rcp(tau + 0.5f);
 
         // gbar collision with the mixed-difference forcing:

@@ -36,9 +36,11 @@ def test_workspace_bytes_valid_and_invalid(L):
     n = pflbm.workspace_bytes([prm])
     assert n > 9 * 2 * 4 * 64 * 128
     bad = [dict(prm, nx=4), dict(prm, n_h=3), dict(prm, rho=[0.0, 1.0, 1.0]), dict(prm, nu_min=2.0, nu_max=1.0,
-           powerlaw_comp=2), dict(prm, tau_h=0.7, store_h=0), dict(prm, sigma23=1.0), dict(prm, xi=0.0)]
+           powerlaw_comp=2), dict(prm, tau_h=0.7, store_h=0), dict(prm, sigma23=1.0), dict(prm, xi=0.0),
+           dict(prm, tau_iterations=-1), dict(prm, tau_iterations=9)]
     for b in bad:
         assert pflbm.workspace_bytes([b]) == 0, b
+    assert pflbm.workspace_bytes([dict(prm, tau_iterations=8)]) == n
     # a stored-hbar case with tau_h != 1/2 is valid
     assert pflbm.workspace_bytes([dict(prm, tau_h=0.7, store_h=1)]) > n
     # batched cases must agree on n_h / storage / store_h

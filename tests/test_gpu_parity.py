@@ -172,6 +172,21 @@ def test_centroid_velocity(torch):
         assert np.abs(g[4:6] - r[4:6]).max() < 1e-5 * np.abs(r[4:6]).max() + 1e-12
 
 
+def test_implicit_tau_passes(torch):
+    """tau_iterations = 3 (fixed-point passes of Eq. (32)) against the oracle,
+    on a power-law bubble whose liquid stays inside the truncation (K = 1e-4)
+    and on the shear-thinning channel; in both the passes move u by far more
+    than the tolerance (1.6e-4 and 7.9e-5 relative in the oracle)."""
+    case = inputs.powerlaw_bubble(n=0.5, nx=100, ny=200, d=50.0, K=1e-4)
+    ch = inputs.channel(0.5, ny=32, nx=5, fx=2e-6, K=0.0025, nu_min=1e-3, nu_max=1.0)
+    for c, steps in ((case, 300), (ch, 2000)):
+        _, m0 = gpu_run(c, steps)
+        c["params"] = dict(c["params"], tau_iterations=3)
+        _, m = gpu_run(c, steps)
+        compare(m, run_case(c, steps).macroscopic())
+        assert rel_l2(m["u"], m0["u"]) > 3e-5
+
+
 def test_rise_velocity_matches_oracle(torch):
     """Mean rise velocity of the small bubble after 1,000 and 1,500 steps:
     GPU within 1e-4 of the oracle (the paper's terminal-velocity comparison

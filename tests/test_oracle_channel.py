@@ -98,3 +98,29 @@ def test_literal_strain_factor_is_rejected_by_the_closed_form():
     # the shear-thinning profile then misses the closed form by far more
     u, ref = run_channel(0.5, strain_literal=1)
     assert rel_l2(u, ref) > 0.03
+
+
+def test_implicit_tau_reaches_the_same_steady_channel():
+    # at steady state the previous step's tau is the fixed point of the
+    # implicit relation (Eq. (32)), so fixed-point passes change nothing there
+    u0, ref = run_channel(0.5)
+    u3, _ = run_channel(0.5, tau_iterations=3)
+    assert rel_l2(u3, ref) < 0.005
+    assert rel_l2(u3, u0) < 1e-6
+
+
+def test_fixed_point_passes_converge():
+    """From rest the shear rate changes every step, so the previous step's
+    tau lags; more fixed-point passes approach the implicit solution: the
+    distance to the 8-pass state shrinks with the number of passes."""
+    K, n, ny = K_FOR_N[0.5], 0.5, 32
+    G = K * (0.01 * (n + 1) / n / (ny / 2.0) ** ((n + 1) / n)) ** n
+    case = inputs.channel(n, ny=ny, nx=5, fx=G, K=K, nu_min=1e-3, nu_max=1.0)
+    prof = {}
+    for m in (0, 1, 2, 4, 8):
+        o = Oracle(dict(case["params"], tau_iterations=m))
+        o.init_fields(case["C"])
+        o.step(40)
+        prof[m] = o.macroscopic()["u"][0][:, 2]
+    d = [np.linalg.norm(prof[m] - prof[8]) for m in (0, 1, 2, 4)]
+    assert d[0] > 0 and all(a > b for a, b in zip(d, d[1:])), d
