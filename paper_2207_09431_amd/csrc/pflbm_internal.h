@@ -9,8 +9,10 @@ namespace pflbm {
 // fused step kernel variants (pflbm_step.hip)
 int step_variant_count();
 bool step_variant_shape(int v, int nh, int* tx, int* ty, int* nt);
-// state forms of the step: compact float32, stored hbar float32, compact float16
-constexpr int kStepForms = 3;
+// state forms of the step: compact float32, stored hbar float32, compact
+// float16 (0..2), and the same with the fixed-point passes of the implicit
+// tau (3..5)
+constexpr int kStepForms = 6;
 hipError_t launch_step(int v, int nh, int form, const CaseDev* cases, const TileDev* tiles, int ntiles, int par,
                        hipStream_t stream);
 

@@ -100,7 +100,7 @@ __device__ __forceinline__ void md_all(const float* f, int i, float d[9], float&
     gy = (1.0f / 3.0f) * (d[2] - d[4]) + (1.0f / 12.0f) * (p5 + p6);
 }
 
-template <int TX, int TY, int NH, bool SH, bool F16, int NT>
+template <int TX, int TY, int NH, bool SH, bool F16, int NT, bool IMPL>
 __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ cases,
                                                   const TileDev* __restrict__ tiles, int ntiles, int par) {
     constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
@@ -418,9 +418,11 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const float pin = sqrtf(2.0f * (pxx * pxx + pyy * pyy + 2.0f * pxy * pxy));
         float tau = mixture_tau(cd, c[0], c[1], c3, fs * pin);
         // optional fixed-point passes of the implicit relation tau = tau(gdot(tau))
-        // (Sec. 2.3, Eq. (32)), started from the previous step's tau
-        for (int it = 0; it < cd.tau_iters; ++it)
-            tau = mixture_tau(cd, c[0], c[1], c3, 4.5f * rcp((tau + 0.5f) * rho) * pin);
+        // (Sec. 2.3, Eq. (32)), started from the previous step's tau; a kernel
+        // instance of its own, so that the default path has no loop here
+        if (IMPL)
+            for (int it = 0; it < cd.tau_iters; ++it)
+                tau = mixture_tau(cd, c[0], c[1], c3, 4.5f * rcp((tau + 0.5f) * rho) * pin);
         const float om = rcp(tau + 0.5f);
 
         // gbar collision with the mixed-difference forcing:
@@ -599,7 +601,8 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
 }
 
 // Step variants selectable at run time: tile shape x phase-field count x
-// state form (compact float32, stored hbar float32, compact float16).  A tile
+// state form (compact float32, stored hbar float32, compact float16; each
+// without and with the fixed-point passes of the implicit tau).  A tile
 // shape whose LDS footprint exceeds the 160 KiB of a gfx950 CU for two phase
 // fields is offered for one phase field only.
 using StepFn = void (*)(const CaseDev*, const TileDev*, int, int);
@@ -608,11 +611,13 @@ struct StepVariant {
     StepFn k[2][kStepForms];   // [n_h - 1][form]
 };
 
-#define PFLBM_K(TX, TY, NH, SH, F16, NT) step_kernel<TX, TY, NH, SH, F16, NT>
-#define PFLBM_FORMS(TX, TY, NH, NT) \
-    {PFLBM_K(TX, TY, NH, false, false, NT), PFLBM_K(TX, TY, NH, true, false, NT), PFLBM_K(TX, TY, NH, false, true, NT)}
+#define PFLBM_K(TX, TY, NH, SH, F16, NT, I) step_kernel<TX, TY, NH, SH, F16, NT, I>
+#define PFLBM_FORMS(TX, TY, NH, NT)                                                                  \
+    {PFLBM_K(TX, TY, NH, false, false, NT, false), PFLBM_K(TX, TY, NH, true, false, NT, false),      \
+     PFLBM_K(TX, TY, NH, false, true, NT, false), PFLBM_K(TX, TY, NH, false, false, NT, true),        \
+     PFLBM_K(TX, TY, NH, true, false, NT, true), PFLBM_K(TX, TY, NH, false, true, NT, true)}
 #define PFLBM_V2(TX, TY, NT) {TX, TY, NT, {PFLBM_FORMS(TX, TY, 1, NT), PFLBM_FORMS(TX, TY, 2, NT)}}
-#define PFLBM_V1(TX, TY, NT) {TX, TY, NT, {PFLBM_FORMS(TX, TY, 1, NT), {nullptr, nullptr, nullptr}}}
+#define PFLBM_V1(TX, TY, NT) {TX, TY, NT, {PFLBM_FORMS(TX, TY, 1, NT), {}}}
 
 static const StepVariant kVariants[] = {
     PFLBM_V2(32, 16, 512),
