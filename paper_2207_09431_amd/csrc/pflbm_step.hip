@@ -11,8 +11,10 @@
 //   C  on the 1-node halo: grad p, grad mu, lap mu, the diffusion source of
 //      Eq. (21), mixed directional derivatives of rho and C_i, the shear rate
 //      from the non-equilibrium second moment with the previous tau
-//      (Eqs. (25)-(29)), the truncated power-law tau (Eqs. (31)-(33)) and the
-//      post-collision populations of gbar (Eq. (14)) and hbar (Eq. (18));
+//      (Eqs. (25)-(29)), the truncated power-law viscosity (Eqs. (31), (33))
+//      mixed harmonically across the interface into tau (optionally with
+//      fixed-point passes of Eq. (32)) and the post-collision populations of
+//      gbar (Eq. (14)) and hbar (Eq. (18));
 //   D  on the tile: gather the post-collision populations (half-way
 //      bounce-back at the walls), add the receiving-node half of the
 //      diffusion term and write the new state.
