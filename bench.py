@@ -127,9 +127,23 @@ def cpu_baseline(seconds):
     t = time.perf_counter()
     o.step(n)
     dt = time.perf_counter() - t
+    # the same oracle on one thread, for a quarter of the time
+    set_threads(1)
+    n1 = max(2, int(0.25 * seconds / max(per * threads, 1e-6)))
+    t = time.perf_counter()
+    o.step(n1)
+    dt1 = time.perf_counter() - t
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{case['name']} (256x512 window of the same seed), {n} steps, float64, "
-                      f"{threads} OpenMP threads"}
+                      f"{threads} OpenMP threads",
+            "single_thread_value": round(cells * n1 / dt1 / 1e6, 3), "single_thread_steps": n1,
+            "cpu_model": model}
 
 
 def batch_forms(torch, Solver, inputs, steps, warmup):
