@@ -48,6 +48,10 @@ def test_workspace_bytes_valid_and_invalid(L):
     assert pflbm.workspace_bytes([prm, dict(prm, nx=80, ny=90)]) > n
     assert pflbm.workspace_bytes([prm, dict(prm, storage=1)]) == 0
     assert pflbm.workspace_bytes([dict(prm, storage=2)]) == 0
+    # the largest domain: pitch x ny just below 2^29 nodes (float64 planes under 4 GiB)
+    assert pflbm.workspace_bytes([dict(prm, nx=16384, ny=32767)]) > 0
+    assert pflbm.workspace_bytes([dict(prm, nx=16384, ny=32768)]) == 0
+    assert pflbm.workspace_bytes([dict(prm, nx=16321, ny=32768)]) == 0   # pitch rounds up to 16384
 
 
 def test_float16_form_is_smaller(L):
