@@ -176,8 +176,14 @@ class Solver:
     def _empty(self, *shape):
         return self.torch.empty(*shape, dtype=self.torch.float32, device=self.device)
 
+    def _case_params(self, case_id, where):
+        # output shapes come from the case; an unknown case is the ABI's INVALID_ARG
+        if not 0 <= int(case_id) < len(self.params):
+            raise PflbmError(where, -1)
+        return self.params[int(case_id)]
+
     def macroscopic(self, case_id=0):
-        prm = self.params[case_id]
+        prm = self._case_params(case_id, "pflbm_macroscopic")
         ny, nx = prm["ny"], prm["nx"]
         out = dict(rho=self._empty(ny, nx), u=self._empty(2, ny, nx), p=self._empty(ny, nx),
                    phi=self._empty(prm["n_h"], ny, nx))
@@ -205,7 +211,7 @@ class Solver:
         _check("pflbm_set_state", lib().pflbm_set_state(self._h, ct.c_void_p(buf.data_ptr()), buf.numel()))
 
     def export_populations(self, case_id=0):
-        prm = self.params[case_id]
+        prm = self._case_params(case_id, "pflbm_export_populations")
         out = self._empty(9 + prm["n_h"] + 1, prm["ny"], prm["nx"])
         _check("pflbm_export_populations",
                lib().pflbm_export_populations(self._h, int(case_id), ct.c_void_p(out.data_ptr())))

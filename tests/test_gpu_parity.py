@@ -243,3 +243,24 @@ def test_error_paths(torch):
     with pytest.raises(PflbmError) as e:
         Solver(dict(case["params"], nx=3))
     assert e.value.status == -1
+
+
+def test_degenerate_calls(torch):
+    """Zero steps leave the state untouched; out-of-range arguments are
+    rejected with INVALID_ARG and leave the context usable."""
+    from paper_2207_09431_amd.pflbm import Solver, PflbmError, lib
+    case = inputs.rising_bubble_small()
+    s, _ = gpu_run(case, 3)
+    before = s.get_state().cpu().numpy()
+    s.step(0)
+    assert np.array_equal(s.get_state().cpu().numpy(), before)
+    for call in (lambda: s.step(-1), lambda: s.set_graph(3), lambda: s.set_graph(-2),
+                 lambda: s.set_variant(len(s.variants())), lambda: s.macroscopic(1),
+                 lambda: s.init_fields(1, case["C"]), lambda: s.bubble_centroid_velocity(0, 3)):
+        with pytest.raises(PflbmError) as e:
+            call()
+        assert e.value.status == -1
+    # all outputs NULL is a no-op
+    assert lib().pflbm_macroscopic(s._h, 0, None, None, None, None) == 0
+    s.step(2)
+    assert np.isfinite(s.macroscopic(0)["u"].cpu().numpy()).all()
