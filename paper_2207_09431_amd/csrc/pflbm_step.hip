@@ -102,6 +102,27 @@ __device__ __forceinline__ void md_all(const float* f, int i, float d[9], float&
     gy = (1.0f / 3.0f) * (d[2] - d[4]) + (1.0f / 12.0f) * (p5 + p6);
 }
 
+// Thread-to-node order on a region of width TX + 2h: the TX middle columns
+// first, a row of TX nodes per TX threads, so that every half-wave (32 lanes)
+// reads 32 consecutive LDS words of one row and the stencil reads of the
+// other regions (row pitches TX + 2..6) meet no bank conflict; the 2h edge
+// columns of every row follow.  Returns the region-linear index.
+template <int TX, int H>
+__device__ __forceinline__ int region_node(int n, int rows, int& rx, int& ry) {
+    constexpr int W = TX + 2 * H;
+    const int main = rows * TX;
+    if (n < main) {
+        ry = n / TX;
+        rx = n - ry * TX + H;
+    } else {
+        const int e = n - main;
+        ry = e / (2 * H);
+        const int c = e - ry * (2 * H);
+        rx = c < H ? c : TX + c;
+    }
+    return ry * W + rx;
+}
+
 template <int TX, int TY, int NH, bool SH, bool F16, int NT, bool IMPL>
 __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ cases,
                                                   const TileDev* __restrict__ tiles, int ntiles, int par) {
@@ -181,8 +202,8 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         // nodes) the rest of the deviations and tau
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
-            const int idx = min(tid + k * NT, N2 - 1);
-            const int ry = idx / W2, rx = idx - ry * W2;
+            int rx, ry;
+            region_node<TX, 2>(min(tid + k * NT, N2 - 1), H2, rx, ry);
             const uint32_t eo = node(rx, ry, 2);
             ps[k] = gld(Pin, eo * 8u);
             if (F16) {
@@ -217,9 +238,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     // overwrites node by node
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-        const int idx = tid + k * NT;
-        if (idx >= N2) continue;
-        const int ry = idx / W2, rx = idx - ry * W2;
+        if (tid + k * NT >= N2) continue;
+        int rx, ry;
+        const int idx = region_node<TX, 2>(tid + k * NT, H2, rx, ry);
         const int i3 = (ry + 1) * W3 + rx + 1;
         const int gyr = y0 - 2 + ry;
         float gcx[2] = {0.f, 0.f}, gcy[2] = {0.f, 0.f}, lc[2] = {0.f, 0.f};
@@ -309,8 +330,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     }
 
     // ---------------- phase C: collisions on R1
-    for (int idx = tid; idx < N1; idx += NT) {
-        const int ry = idx / W1, rx = idx - ry * W1;
+    for (int n = tid; n < N1; n += NT) {
+        int rx, ry;
+        const int idx = region_node<TX, 1>(n, H1, rx, ry);
         const int gyr = y0 - 1 + ry;
         if (gyr < 0 || gyr >= ny) continue;   // nodes beyond the walls are never sources
         const int i2 = (ry + 1) * W2 + rx + 1;
