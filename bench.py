@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0
 # read for a 512 MiB device copy (x 2.0 and x 1.0).  Valid only for the kernel
 # sources they were taken on (sha256 prefix of pflbm_step.hip + pflbm_device.h)
 # and the same tile variant; otherwise the bench reports null.
-MEASURED_TRAFFIC = {"source_sha256": "3dd3ffdf2851873d", "variant": "tile32x16_t512",
+MEASURED_TRAFFIC = {"source_sha256": "b93a75b291264bae", "variant": "tile32x16_t512",
                     "nx": 2048, "ny": 4096, "bytes_per_launch": 899.7e6}
 
 

@@ -173,8 +173,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     // ---------------- phase A: C_i and rho on R3
     // All global loads of phases A and B are issued here, phase A's first, so
     // that the latency of the gbar loads (consumed in phase B) overlaps
-    // phase A.  Each thread owns the nodes idx = tid + k NT of each region.
-    // The loads are unconditional (surplus threads and rows beyond the walls
+    // phase A.  Thread tid owns the R3 nodes idx = tid + k NT (linear order)
+    // and the R2 nodes numbered tid + k NT in the row order of region_node,
+    // the order in which phase B consumes them.  The loads are unconditional (surplus threads and rows beyond the walls
     // read a valid node and discard it) so that no branch forces an early wait.
     constexpr int KA = (N3 + NT - 1) / NT, KB = (N2 + NT - 1) / NT;
     constexpr int ND = F16 ? 2 + kQPlanes : 8;
