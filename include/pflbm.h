@@ -200,7 +200,15 @@ void* pflbm_stream(const pflbm_ctx* ctx);
 /* Algorithmic bytes moved per lattice update by the step kernel. */
 double pflbm_bytes_per_update(const pflbm_ctx* ctx);
 
+/*
+ * Destroys any captured hipGraph, waits for the context's stream and frees
+ * the host-side context (the caller's workspace is left alone).  Errors:
+ * INVALID_ARG for NULL; DEVICE when the final synchronisation fails (the
+ * context is freed either way).
+ */
 int32_t pflbm_destroy(pflbm_ctx* ctx);
+
+/* Static text for a pflbm_status value ("unknown status" otherwise). */
 const char* pflbm_status_string(int32_t status);
 
 #ifdef __cplusplus
