@@ -67,3 +67,14 @@ def test_float16_form_is_smaller(L):
 def test_status_strings(L):
     for s in (0, -1, -2, -3, -4, -5, -6):
         assert L.pflbm_status_string(s)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library every call raises: there is no fallback."""
+    monkeypatch.setattr(pflbm, "_lib", None)
+    monkeypatch.setattr(pflbm, "LIB_PATH", str(tmp_path / "libpflbm.so"))
+    prm = inputs.rising_bubble_small()["params"]
+    with pytest.raises(RuntimeError, match="missing"):
+        pflbm.workspace_bytes([prm])
+    with pytest.raises(RuntimeError, match="missing"):
+        pflbm.Solver(prm)
