@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and stored-hbar forms")
+    ap.add_argument("--storage", type=int, default=0, choices=(0, 1),
+                    help="state form of the timed workload: 0 float32 deviations, 1 float16 pair moments")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -55,8 +57,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(variant, nx, ny):
+def measured_traffic(variant, nx, ny, storage=0):
     m = MEASURED_TRAFFIC
+    if storage != 0:
+        return None
     try:
         same = kernel_source_hash() == m["source_sha256"]
     except OSError:
@@ -193,7 +197,7 @@ def main():
     from paper_2207_09431_amd.pflbm import Solver
 
     case = inputs.many_bubbles(a.nx, a.ny, a.bubbles)
-    prm = dict(case["params"])
+    prm = dict(case["params"], storage=a.storage)
     s = Solver(prm, device="cuda:0")
     s.init_fields(0, case["C"], case["u"], case["p"])
     if a.variant >= 0:
@@ -227,13 +231,16 @@ def main():
         "config": {
             "workload": f"{case['name']}: {a.nx}x{a.ny} single domain, {a.bubbles} seeded bubbles R 25-40, "
                         f"power-law liquid n=0.6 K=0.1, density ratio 1000, float32 arithmetic, "
-                        f"state: gbar level float64 + 8 deviations float32, C float64, tau float32 (tau_h = 1/2)",
+                        + ("state: gbar level float64 + 8 deviations float32, C float64, tau float32 (tau_h = 1/2)"
+                           if a.storage == 0 else
+                           "state: gbar level float64 + momentum float32 + 6 float16 pair moments, C float64, "
+                           "tau float32 (tau_h = 1/2)"),
             "nx": a.nx, "ny": a.ny, "cells": cells, "bytes_per_update": bpu, "kernel_variant": variant,
             "autotune_ms_per_step": tuning, "wall_s_timed": round(wall, 4), "gas_mass": diag[0],
         },
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(variant, a.nx, a.ny)},
+                     "traffic": measured_traffic(variant, a.nx, a.ny, a.storage)},
     }
     del s
     torch.cuda.empty_cache()
