@@ -7,7 +7,7 @@ consistency K3, index n3) for |y| < Y_i = H/2 and component 1 (Newtonian,
 nu1) outside, both of density 1.  The stress is tau_xy = -G y in both, so the
 local shear rate solves nu(gdot) gdot = G |y| with the law of the layer at
 |y|, and u(y) = int_|y|^H gdot(s) ds.  Without truncation this is the
-paper's layered profile: inside, the power-law part
+paper's layered profile (Sec. 3.3, Eq. (36)): inside, the power-law part
 n3/(n3+1) (G/K3)^(1/n3) (Y_i^((n3+1)/n3) - |y|^((n3+1)/n3)) plus the outer
 layer's velocity at Y_i; outside, n1/(n1+1) (G/mu1)^(1/n1)
 (H^((n1+1)/n1) - |y|^((n1+1)/n1)).  (The printed equation writes Y_i where

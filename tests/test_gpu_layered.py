@@ -1,6 +1,7 @@
 """GPU runs of the two-layer flow of Sec. 3.3 (Fig. 6) on the paper's 5 x 200
 lattice, advanced to steady state and compared with the layered closed form
-(tests/layered.py), the paper's Table 3 errors as bounds (tests/golden); and
+(Eq. (36), tests/layered.py) in the relative L2 norm of Eq. (35), the
+paper's Table 3 errors as bounds (tests/golden); and
 GPU-oracle parity on the same setup.
 
 Setup (the paper leaves it open): outer Newtonian layer nu1 = 1/6, inner
