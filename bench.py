@@ -150,6 +150,27 @@ def cpu_baseline(seconds):
             "cpu_model": model}
 
 
+def small_configs(torch, Solver, inputs, steps, warmup):
+    """The smaller configurations (cache-resident, launch-bound): the 64 x 128
+    rising bubble, a 200 x 400 power-law bubble (d = 40) and the 256 x 512
+    three-component case; plain launches and 10-step hipGraph replay."""
+    out = {}
+    for name, case in (("rising_bubble_64x128", inputs.rising_bubble_small()),
+                       ("powerlaw_bubble_200x400", inputs.powerlaw_bubble(n=0.8, d=40.0)),
+                       ("three_component_256x512", inputs.three_component())):
+        s = Solver(case["params"])
+        s.init_fields(0, case["C"], case["u"], case["p"])
+        var = s.autotune(steps=3)
+        cells = case["params"]["nx"] * case["params"]["ny"]
+        ms, _ = timed_steps(torch, [s], steps, warmup)
+        s.set_graph(10)
+        ms_g, _ = timed_steps(torch, [s], steps - steps % 10, 10)
+        out[name] = {"mlups": round(cells / (ms * 1e-3) / 1e6, 1), "graph_mlups": round(cells / (ms_g * 1e-3) / 1e6, 1),
+                     "ms_per_step": round(ms, 4), "variant": var, "bytes_per_update": s.bytes_per_update()}
+        s.close()
+    return out
+
+
 def batch_forms(torch, Solver, inputs, steps, warmup):
     """48 uneven bubble cases (16 each of 150x300, 200x400, 300x600): one
     batched launch per step vs the same cases advanced one by one."""
@@ -267,6 +288,7 @@ def main():
                                     "variant": qvar, "bytes_per_update": sq.bytes_per_update(),
                                     "achieved_GBs": round(sq.bytes_per_update() * cells / (ms_q * 1e-3) / 1e9, 1)}
         del sq
+        forms["small_configs"] = small_configs(torch, Solver, inputs, max(100, a.steps), 20)
         out["forms"] = forms
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
