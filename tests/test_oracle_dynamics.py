@@ -51,6 +51,27 @@ def mass(o, comp=0):
     return o.centroid(comp)[0]
 
 
+
+@pytest.mark.parametrize("g", [1e-5, -1e-5])
+def test_hydrostatic_column_is_exact_fixed_point(g):
+    """Liquid at rest under the body force F_b = -rho g j (Eq. (12)) between
+    the walls, started from its hydrostatic pressure p = rho g (y_c - y): an
+    exact steady state (the linear pressure streams exactly and balances the
+    force term), so u stays at round-off and the pressure slope is -rho g.
+    A wrong sign or factor of the body force in the forcing, the momentum
+    moment or the pressure moment breaks it."""
+    nx, ny = 5, 32
+    prm = inputs.default_params(nx, ny)
+    prm.update(rho=[1e-3, 1e-3, 1.0], g=g, variable_mobility=0)
+    C = np.zeros((1, ny, nx))
+    o = Oracle(prm)
+    o.init_fields(C, None, inputs.hydrostatic_pressure(C, prm))
+    o.step(500)
+    m = o.macroscopic()
+    assert np.abs(m["u"]).max() < 1e-17
+    slope = np.diff(m["p"], axis=0)
+    assert np.abs(slope + g).max() < 1e-17
+
 @pytest.mark.parametrize("vm,flux", [(0, 0), (1, 1)])
 def test_mass_exact_with_central_hbar_forcing(vm, flux):
     case = inputs.rising_bubble_small()
@@ -119,3 +140,27 @@ def test_thread_count_does_not_change_results():
         set_threads(keep)
     for k in ("u", "p", "phi", "rho"):
         assert np.array_equal(out[0][k], out[1][k]), k
+
+
+def test_accelerated_slab_moves_with_the_fluid():
+    """Equal densities and a body force f along the periodic x accelerate the
+    fluid uniformly away from the walls, u = f t, so a slab of component 1
+    is carried by f N^2 / 2 in N steps.  The C flux under acceleration comes
+    partly from the pressure and force term of the hbar forcing (Eq. (18));
+    with its sign flipped the slab lags by 2 %."""
+    nx, ny, f, N = 64, 64, 1e-6, 200
+    prm = inputs.default_params(nx, ny)
+    prm.update(rho=[1.0, 1.0, 1.0], nu=[1 / 6, 1 / 6, 1 / 6], fx=f, g=0.0, variable_mobility=0)
+    x = np.arange(nx, dtype=np.float64)
+    c = 0.5 * (np.tanh((x - 16) / 2.0) - np.tanh((x - 48) / 2.0))
+    o = Oracle(prm)
+    o.init_fields(np.repeat(c[None, :], ny, axis=0)[None])
+    rows = slice(ny // 2 - 8, ny // 2 + 8)      # away from the walls' boundary layers
+
+    def centroid():
+        m = o.macroscopic()["phi"][0][rows]
+        return (m * x[None, :]).sum() / m.sum()
+
+    x0 = centroid()
+    o.step(N)
+    assert abs((centroid() - x0) / (0.5 * f * N * N) - 1) < 5e-3
