@@ -146,16 +146,17 @@ def test_batch_48_matches_single_runs_and_oracle(torch):
         assert ru <= 1e-5 and rc <= 1e-5
 
 
-def test_large_domain_10k_steps_at_density_ratio_100(torch):
+@pytest.mark.parametrize("storage", [0, 1])
+def test_large_domain_10k_steps_at_density_ratio_100(torch, storage):
     """The 2048 x 4096 workload for the 10,000 steps of its configuration, at
     density ratio 100: at 1000 the method as read diverges after a few
     thousand steps on this domain (the oracle diverges with the GPU on a
     1024 x 1024 single-bubble case), at 100 it stays bounded.  Checks: finite,
     below the low-Mach bound, the bubbles rise, and the gas mass, summed in
-    float64, changes by less than 1e-7 of itself."""
+    float64, changes by less than 1e-7 of itself; in both storage forms."""
     from paper_2207_09431_amd.pflbm import Solver
     case = inputs.many_bubbles(density_ratio=100.0, at_rest=True)
-    s = Solver(case["params"])
+    s = Solver(dict(case["params"], storage=storage))
     s.init_fields(0, case["C"], None, case["p"])
     m0 = s.bubble_centroid_velocity(0, 0)
     for k in range(10):
