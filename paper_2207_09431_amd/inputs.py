@@ -182,6 +182,22 @@ def rising_bubble_small(seed: int = 1, nx: int = 64, ny: int = 128, density_rati
     return _case(prm, C, u, hydrostatic_pressure(C, prm), f"rising_bubble_{nx}x{ny}")
 
 
+def rising_bubble_terminal(nx: int = 128, ny: int = 512, radius: float = 24.0) -> dict:
+    """A larger bubble of the small case's fluids (density ratio 100, Newtonian,
+    nu_l = 0.8/3, nu_g = 10 nu_l, D0 = 0.02 constant mobility, sigma = 1e-3,
+    g from Eo = 10 on d = 2R) at (nx/2, ny/5), hydrostatic p, no noise.  Its
+    mean rise velocity levels off after ~6,000 steps and then drifts by
+    ~0.1 % per 1,000 steps as the bubble slowly dissolves (constant mobility),
+    which gives the terminal-velocity comparison a plateau."""
+    prm = default_params(nx, ny)
+    nu_l = 0.8 / 3.0
+    rg = 1.0 / 100.0
+    prm.update(rho=[rg, rg, 1.0], nu=[10.0 * nu_l, 10.0 * nu_l, nu_l], powerlaw_comp=-1, n=1.0,
+               D0=0.02, variable_mobility=0, g=gravity_from_eotvos(10.0, 1e-3, 1.0, rg, 2.0 * radius))
+    C = bubble_field(nx, ny, [(nx / 2.0, ny / 5.0, radius)], prm["xi"])[None]
+    return _case(prm, C, None, hydrostatic_pressure(C, prm), f"rising_bubble_terminal_{nx}x{ny}_R{radius:g}")
+
+
 def static_bubble(nx: int = 96, ny: int = 96, radius: float = 25.0, density_ratio: float = 1000.0,
                   sigma: float = 1e-4, variable_mobility: int = 0) -> dict:
     """Bubble at rest in the middle of the box, no gravity."""

@@ -2,6 +2,9 @@
 same seeded inputs.  Float32 arithmetic (float32 gbar state, float64 C state):
 relative L2 of u and C <= 1e-5 after the stated number of steps.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -290,3 +293,30 @@ def test_hydrostatic_column_and_accelerated_slab(torch):
     case = dict(params=prm, C=np.repeat(c[None, :], ny, axis=0)[None], u=None, p=None)
     _, m = gpu_run(case, 200)
     compare(m, run_case(case, 200).macroscopic())
+
+
+
+def test_terminal_velocity_within_half_percent(torch):
+    """Mean rise velocity (Eq. (44)) of a bubble on its plateau (128 x 512,
+    R = 24, density ratio 100; steps 8,000-10,000, where it changes by a few
+    tenths of a percent): the GPU within 0.5 % of the oracle at each of three
+    samples.  The oracle's values are stored in tests/golden (written by
+    make_terminal_velocity.py there, which calls only the oracle): its
+    10,000 steps take minutes on the CPU."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "terminal_velocity.json")) as f:
+        ref = json.load(f)["samples"]
+    case = inputs.rising_bubble_terminal()
+    print(f"case {case['name']}", flush=True)
+    s, _ = gpu_run(case, 0)
+    done, g = 0, []
+    for row in ref:
+        s.step(row["step"] - done)
+        done = row["step"]
+        out = s.bubble_centroid_velocity(0, 0)
+        g.append((out[5], out[3]))
+    r = [(row["V_y"], row["y_c"]) for row in ref]
+    print("V_y, y_c gpu " + " ".join(f"{v:.6e},{y:.4f}" for v, y in g)
+          + " oracle " + " ".join(f"{v:.6e},{y:.4f}" for v, y in r), flush=True)
+    assert abs(r[-1][0] / r[0][0] - 1) < 1e-2           # on the plateau
+    assert all(abs(a[0] / b[0] - 1) < 5e-3 for a, b in zip(g, r))
+    assert all(abs(a[1] - b[1]) < 0.05 for a, b in zip(g, r))
