@@ -226,6 +226,34 @@ def powerlaw_bubble(n: float = 0.5, eo: float = 10.0, nx: int = 200, ny: int = 4
     return _case(prm, C, None, None, f"powerlaw_bubble_{nx}x{ny}_n{n:.3f}_Eo{eo:.2f}")
 
 
+
+# Table 5 (Sec. 4.3): power-law index n, consistency k, gravity g, surface
+# tension sigma of the six shear-thinning cases (d_b = L/4 = 50, tau_d = 0.5)
+TABLE5_FLUIDS = ((0.5, 1e-4, 5e-7, 2.61e-6), (0.5, 1e-4, 5e-7, 2.61e-5), (0.5, 2e-4, 5e-7, 5e-4),
+                 (0.6, 5e-4, 2e-7, 2.61e-5), (0.63, 5e-4, 2e-7, 2.61e-5), (0.8, 1e-2, 5e-7, 2.61e-5))
+
+
+def shear_thinning_sweep(density_ratio: float = 800.0, nx: int = 200, ny: int = 400) -> list:
+    """The six bubbles of Table 5: d = nx/4 at (nx/2, 0.6 nx) (Eq. (42)) in a
+    power-law liquid (rho_l = 1) with the printed n, k, g and sigma; gas
+    nu = c_s^2 * 0.5 (tau_d = 0.5), nu in [1e-4, 1], constant mobility
+    xi/300, the bubble started at its rest pressure.  The paper's density
+    ratio is 800."""
+    out = []
+    d = nx / 4.0
+    for i, (n, k, g, sigma) in enumerate(TABLE5_FLUIDS):
+        prm = default_params(nx, ny)
+        rg = 1.0 / density_ratio
+        prm.update(rho=[rg, rg, 1.0], nu=[1.0 / 6.0, 1.0 / 6.0, 1.0], powerlaw_comp=2,
+                   K=k, n=n, nu_min=1e-4, nu_max=1.0, variable_mobility=0,
+                   sigma12=sigma, sigma13=sigma, sigma23=sigma, g=g)
+        b = [(nx / 2.0, 0.6 * nx, d / 2.0)]
+        C = bubble_field(nx, ny, b, prm["xi"])[None]
+        p = rest_pressure(nx, ny, b, prm["xi"], sigma, 1.0, g)
+        out.append(_case(prm, C, None, p, f"table5_case{i + 1}_{nx}x{ny}_ratio{density_ratio:g}"))
+    return out
+
+
 def three_component(variable_mobility: int = 0, nx: int = 256, ny: int = 512) -> dict:
     """Three components: C1 bubble R=40 at (128,160), C2 bubble R=25 at
     (128,330) above it, liquid C3 power law n=0.7, K=0.1, both dispersed

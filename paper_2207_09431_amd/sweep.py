@@ -1,0 +1,102 @@
+"""Terminal velocities of a set of rising bubbles (Sec. 4.3), advanced
+together in one batched solver on the GPU, with the drag post-processing of
+Sec. 4.1.
+
+    python -m paper_2207_09431_amd.sweep [--ratio 200] [--cases 3,4,5,6] [--steps 60000]
+
+prints one JSON object per case.  The terminal velocity is read as the
+largest sampled mean rise velocity (Eq. (44)) before the bubble comes within
+one diameter of the top wall: with constant mobility the gas slowly dissolves
+after the plateau, so the velocity peaks on it and then drifts down.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+
+from . import drag, inputs
+from .pflbm import PflbmError, Solver
+
+
+def run_sweep(cases: list, max_steps: int, every: int = 1000) -> list:
+    """Advances all `cases` (single-bubble cases, component 0 the gas) in one
+    batched solver for up to `max_steps` steps, sampling the bubble
+    diagnostics every `every` steps, and returns per case the samples and the
+    report at the terminal sample (None when the case became non-finite or
+    never peaked), and why sampling ended ("max_steps", "top_wall" or
+    "nonfinite by step N")."""
+    s = Solver([c["params"] for c in cases])
+    for i, c in enumerate(cases):
+        s.init_fields(i, c["C"], c.get("u"), c.get("p"))
+    samples = [[] for _ in cases]
+    alive = [True] * len(cases)
+    end = ["max_steps"] * len(cases)
+    done = 0
+    while done < max_steps and any(alive):
+        s.step(every)
+        done += every
+        for i, c in enumerate(cases):
+            if not alive[i]:
+                continue
+            try:
+                diag = s.bubble_centroid_velocity(i, 0)
+            except PflbmError:
+                alive[i] = False
+                end[i] = f"nonfinite by step {done}"
+                continue
+            d = drag.equivalent_diameter(diag[0])
+            if diag[3] + 1.5 * d > c["params"]["ny"]:
+                alive[i] = False            # within a diameter of the top wall
+                end[i] = "top_wall"
+                continue
+            samples[i].append((done, [float(v) for v in diag]))
+    out = []
+    for i, c in enumerate(cases):
+        res = {"case": c["name"], "steps": samples[i][-1][0] if samples[i] else 0, "end": end[i],
+               "samples": samples[i], "report": None}
+        if samples[i] and not end[i].startswith("nonfinite"):
+            k = max(range(len(samples[i])), key=lambda j: samples[i][j][1][5])
+            if 0 < k < len(samples[i]) - 1:
+                step, diag = samples[i][k]
+                res["peak_step"] = step
+                res["plateau_change"] = max(abs(samples[i][k + j][1][5] / diag[5] - 1) for j in (-1, 1))
+                res["diag"] = diag
+        out.append(res)
+    # the shape at each case's peak: a second, bitwise identical run of the
+    # batch stops at the peak steps in increasing order and copies the gas
+    # fraction of the case that peaked there
+    order = sorted((r["peak_step"], i) for i, r in enumerate(out) if "peak_step" in r)
+    if order:
+        s2 = Solver([c["params"] for c in cases])
+        for i, c in enumerate(cases):
+            s2.init_fields(i, c["C"], c.get("u"), c.get("p"))
+        at = 0
+        for step, i in order:
+            if step > at:
+                s2.step(step - at)
+                at = step
+            prm = cases[i]["params"]
+            phi = s2.macroscopic(i)["phi"][0].cpu().numpy()
+            out[i]["report"] = drag.bubble_report(out[i]["diag"], phi, prm["rho"][2], prm["rho"][0], prm["g"],
+                                                  prm["sigma13"], prm["K"], prm["n"])
+    return out
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--ratio", type=float, default=200.0, help="liquid/gas density ratio (the paper's is 800)")
+    ap.add_argument("--cases", default="1,2,3,4,5,6", help="Table 5 cases to run (1-based)")
+    ap.add_argument("--steps", type=int, default=60000)
+    ap.add_argument("--every", type=int, default=1000)
+    a = ap.parse_args(argv)
+    all_cases = inputs.shear_thinning_sweep(density_ratio=a.ratio)
+    pick = [int(x) - 1 for x in a.cases.split(",")]
+    for r in run_sweep([all_cases[i] for i in pick], a.steps, a.every):
+        r = dict(r)
+        r.pop("samples")
+        print(json.dumps(r), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

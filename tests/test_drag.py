@@ -1,0 +1,129 @@
+"""Pins of the drag post-processing (Sec. 4.1, Eqs. (37)-(41)) against the
+values the paper prints and against limits with textbook forms.  Host code
+only (no GPU, no oracle: these are formulas on the diagnostics)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2207_09431_amd import drag, inputs
+
+# Table 5 (n, k, g, sigma) with d_b = L/4 = 50, rho_l = 1, and the printed
+# results: Table 6's Re and Eo, Table 7's simulated terminal velocity
+TABLE5 = [(0.5, 1e-4, 5e-7, 2.61e-6), (0.5, 1e-4, 5e-7, 2.61e-5), (0.5, 2e-4, 5e-7, 5e-4),
+          (0.6, 5e-4, 2e-7, 2.61e-5), (0.63, 5e-4, 2e-7, 2.61e-5), (0.8, 1e-2, 5e-7, 2.61e-5)]
+TABLE6_RE = [4.05, 4.29, 1.36, 0.44, 0.99, 0.47]
+TABLE6_EO = [478.9, 47.89, 2.5, 19.15, 19.15, 47.89]
+TABLE7_U = [0.00156, 0.00157, 0.0011, 0.00046, 0.00063, 0.00085]
+
+
+def test_eotvos_reproduces_table6():
+    """All six printed Eo follow from Eq. (40) with d = d_b = 50 and rho_l = 1
+    standing for the density difference, to one unit of the last printed
+    digit (19.157 is printed 19.15); with rho_l - rho_g = 799/800 case 1
+    would read 478.3."""
+    for (n, k, g, s), eo in zip(TABLE5, TABLE6_EO):
+        val = drag.eotvos(1.0, g, 50.0, s)
+        digits = len(f"{eo}".split(".")[1])
+        assert abs(val - eo) < 10.0 ** -digits, (val, eo)
+    n, k, g, s = TABLE5[0]
+    assert abs(drag.eotvos(799 / 800, g, 50.0, s) - TABLE6_EO[0]) > 0.5
+
+
+def test_reynolds_reproduces_table6_where_consistent():
+    """Eq. (38) with Table 7's simulated U and d = 50 gives Table 6's Re for
+    cases 4 and 6 to the printed digits and case 5 within 3 %; cases 1-3 are
+    5-8 % off whatever U of Table 7 is used (the printed values do not fix
+    them).  The exponents are checked: swapping U^(2-n) and d^n misses by
+    orders of magnitude."""
+    for c in (3, 5):
+        n, k, g, s = TABLE5[c]
+        assert round(drag.reynolds(1.0, TABLE7_U[c], 50.0, k, n), 2) == TABLE6_RE[c]
+    n, k, g, s = TABLE5[4]
+    assert drag.reynolds(1.0, TABLE7_U[4], 50.0, k, n) == pytest.approx(TABLE6_RE[4], rel=0.03)
+    n, k, g, s = TABLE5[3]
+    assert abs(math.log10(1.0 * 50.0 ** (2 - n) * TABLE7_U[3] ** n / k / TABLE6_RE[3])) > 2
+
+
+def test_newtonian_limits():
+    """n = 1: Re = U d / nu, Mo = g drho mu^4 / (rho^2 sigma^3); with E = 1
+    the correlation is 16/Re (1 + 0.43 Re^0.44)."""
+    U, d, nu, g, s = 2e-3, 40.0, 0.05, 1e-5, 1e-3
+    assert drag.reynolds(1.0, U, d, nu, 1.0) == pytest.approx(U * d / nu, rel=1e-15)
+    assert drag.morton(g, 0.99, 1.0, s, nu, U, d, 1.0) == pytest.approx(g * 0.99 * nu ** 4 / s ** 3, rel=1e-14)
+    Re = 3.7
+    assert drag.li_drag_coefficient(Re, 0.7, 1.0) == pytest.approx(16 / Re * (1 + 0.43 * Re ** 0.44), rel=1e-15)
+    assert drag.li_drag_coefficient(Re, 0.7, 1.3) == drag.li_drag_coefficient(Re, 0.7, 1.0)
+    # a flatter bubble (smaller E) has the larger drag
+    assert drag.li_drag_coefficient(Re, 0.7, 0.8) > drag.li_drag_coefficient(Re, 0.7, 0.95)
+
+
+def test_force_balance():
+    """C_D of Eq. (37) is the drag of a body whose buoyancy it balances:
+    C_D * (1/2) rho_l U^2 * (pi d^2 / 4) = drho g (pi d^3 / 6)."""
+    d, g, rl, rg, U = 50.0, 5e-7, 1.0, 1 / 800, 1.3e-3
+    cd = drag.drag_coefficient(d, g, rl, rg, U)
+    assert cd * 0.5 * rl * U * U * math.pi * d * d / 4 == pytest.approx((rl - rg) * g * math.pi * d ** 3 / 6, rel=1e-14)
+
+
+def test_li_terminal_velocity_solves_the_balance():
+    """The returned U makes Eq. (37) equal Eq. (41); for Stokes-like drag
+    (n = 1, E = 1, Re -> 0) it tends to the closed form of 16/Re = C_D,
+    U = drho g d^2 / (12 mu)."""
+    for (n, k, g, s) in TABLE5:
+        for E in (0.77, 0.95, 1.0):
+            U = drag.li_terminal_velocity(50.0, g, 1.0, 1 / 800, k, n, E)
+            Re = drag.reynolds(1.0, U, 50.0, k, n)
+            assert drag.drag_coefficient(50.0, g, 1.0, 1 / 800, U) == \
+                pytest.approx(drag.li_drag_coefficient(Re, n, E), rel=1e-12)
+    mu, g, d = 10.0, 1e-9, 10.0
+    U = drag.li_terminal_velocity(d, g, 1.0, 0.0, mu, 1.0, 1.0)
+    assert U == pytest.approx(g * d * d / (12 * mu), rel=1e-3)
+
+
+def test_equivalent_diameter_and_shape_of_an_ellipse():
+    """A tanh-profiled ellipse with semi-axes a (x) and b (y): the C = 1/2
+    diameters are 2a and 2b to within the interpolation error, E = b/a, and
+    the summed gas fraction gives the area pi a b (to O(xi^2/(ab))), so d_e
+    is the diameter of that area."""
+    ny, nx, a, b, xc, yc, xi = 240, 200, 30.0, 22.0, 100.3, 110.6, 4.0
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    r = np.sqrt(((x - xc) / a) ** 2 + ((y - yc) / b) ** 2)
+    phi = 0.5 - 0.5 * np.tanh((r - 1.0) * math.sqrt(a * b) / (0.5 * xi))
+    sh = drag.bubble_shape(phi, xc, yc)
+    assert sh["horizontal"] == pytest.approx(2 * a, abs=0.15)
+    assert sh["vertical"] == pytest.approx(2 * b, abs=0.15)
+    assert sh["E"] == pytest.approx(b / a, rel=0.01)
+    assert drag.equivalent_diameter(phi.sum()) == pytest.approx(2 * math.sqrt(a * b), rel=0.01)
+    # the x direction wraps: the same bubble across the periodic seam
+    sh2 = drag.bubble_shape(np.roll(phi, 95, axis=1), (xc + 95) % nx, yc)
+    assert sh2["horizontal"] == pytest.approx(sh["horizontal"], abs=1e-9)
+    with pytest.raises(ValueError):
+        drag.bubble_shape(phi, 5.0, 5.0)
+
+
+def test_report_of_a_synthetic_bubble():
+    """bubble_report on a round bubble of the sweep's recipe: E = 1, d_e = d,
+    Eo of Eq. (40) on that diameter."""
+    case = inputs.shear_thinning_sweep(density_ratio=200.0)[3]
+    prm = case["params"]
+    phi = case["C"][0]
+    diag = (phi.sum(), 0.0, 100.0, 120.0, 0.0, 7e-4)
+    rep = drag.bubble_report(diag, phi, prm["rho"][2], prm["rho"][0], prm["g"], prm["sigma13"],
+                             prm["K"], prm["n"])
+    assert rep["E"] == pytest.approx(1.0, abs=0.01)
+    assert rep["d_e"] == pytest.approx(50.0, rel=0.01)
+    assert rep["Eo"] == pytest.approx((1 - 1 / 200) * 2e-7 * 2500 / 2.61e-5, rel=0.02)
+    assert rep["U"] == 7e-4
+
+
+def test_sweep_recipe_is_table5():
+    """The sweep's fluids are the printed Table 5 rows, and its bubbles have
+    d_b = L/4 = 50 at (0.5 L, 0.6 L) on the 200 x 400 lattice."""
+    assert inputs.TABLE5_FLUIDS == tuple(TABLE5)
+    for c, (n, k, g, s) in zip(inputs.shear_thinning_sweep(), TABLE5):
+        prm = c["params"]
+        assert (prm["n"], prm["K"], prm["g"], prm["sigma13"]) == (n, k, g, s)
+        assert prm["rho"][2] / prm["rho"][0] == pytest.approx(800.0)
+        assert c["C"].shape == (1, 400, 200) and c["C"][0, 120, 100] > 0.99
+        assert c["C"][0, 120, 100 + 27] < 0.5 < c["C"][0, 120, 100 + 24]
