@@ -6,9 +6,9 @@ Each mutation plants one plausible mistake in a copy of oracle/pfo.c (a
 dropped term, a wrong sign or factor, a wrong index), builds it with the
 oracle's own flags, and runs the CPU pins (tests/test_oracle_*.py) against
 it through PFO_LIBRARY.  Every mutation must make at least one pin fail; the
-script prints which test caught it and exits non-zero if one survives.  The
-mutations in UNPINNED touch a part with no closed form (stated as unpinned)
-and are expected to survive.
+script prints which test caught it and exits non-zero if one survives.
+Mutations listed in UNPINNED would touch a part with no closed form (stated
+as unpinned) and be expected to survive; there are none at present.
 """
 import os
 import shutil
@@ -61,14 +61,14 @@ MUTATIONS = [
      [("wrapx(x - EX[a], nx); sa = a;", "wrapx(x + EX[a], nx); sa = a;")]),
     ("hbar relaxation rate 1/tau_h instead of 1/(tau_h + 1/2)",
      [("1.0 / (P->tau_h + 0.5)", "1.0 / P->tau_h")]),
-]
-
-# Mistakes in parts that no closed form or invariant reaches (their parity is
-# stated as unpinned); run to show that they do survive.
-UNPINNED = [
     ("gradient part of the variable-mobility source dropped",
      [("v += c->p.D0 / S[i] * (ax", "v += 0.0 * c->p.D0 / S[i] * (ax")]),
 ]
+
+# Mistakes in parts that no closed form or invariant reaches (their parity is
+# stated as unpinned); run to show that they do survive.  Empty since the
+# one-step diffusion-source pin reaches the variable-mobility gradient term.
+UNPINNED = []
 
 
 def build(src_text, tmp):
