@@ -36,29 +36,32 @@ def test_shear_thinning_bubbles_reach_terminal_velocity(torch):
         assert 1e-4 < rep["U"] < 1e-2
 
 
-def test_shear_thinning_terminal_velocity_matches_oracle(torch):
+@pytest.mark.parametrize("storage", [0, 1])
+def test_shear_thinning_terminal_velocity_matches_oracle(torch, storage):
     """Table 5's case 4 at density ratio 200: the batched sweep's samples of
     the mean rise velocity and centroid against the oracle's (stored in
     tests/golden by make_sweep_terminal.py, which calls only the oracle; its
     46,000 steps take half an hour on the CPU), every 1,000 steps from
-    10,000 on, and the terminal velocity (the peak) within 0.5 %."""
+    10,000 on, and the terminal velocity (the peak) within 0.5 %; in both
+    storage forms."""
     import json
     import os
     from paper_2207_09431_amd.sweep import run_sweep
     with open(os.path.join(os.path.dirname(__file__), "golden", "sweep_case4_terminal.json")) as f:
         ref = json.load(f)["samples"]
     case = inputs.shear_thinning_sweep(density_ratio=200.0)[3]
-    print(f"case {case['name']}", flush=True)
+    case["params"]["storage"] = storage
+    print(f"case {case['name']} storage {storage}", flush=True)
     r = run_sweep([case], ref[-1]["step"], 1000)[0]
     got = {step: diag for step, diag in r["samples"]}
-    worst = 0.0
+    worst, worst_y = 0.0, 0.0
     for row in ref:
         if row["step"] < 10000:
             continue
         v, y = got[row["step"]][5], got[row["step"]][3]
         worst = max(worst, abs(v / row["V_y"] - 1))
-        assert abs(y - row["y_c"]) < 0.05, (row["step"], y, row["y_c"])
+        worst_y = max(worst_y, abs(y - row["y_c"]))
     peak_ref = max(row["V_y"] for row in ref)
-    print(f"worst V_y deviation {worst:.2e}; terminal gpu {r['report']['U']:.6e} oracle {peak_ref:.6e}", flush=True)
-    assert worst < 5e-3
+    print(f"worst V_y deviation {worst:.2e}, y_c {worst_y:.2e}; terminal gpu {r['report']['U']:.6e} oracle {peak_ref:.6e}", flush=True)
+    assert worst < 5e-3 and worst_y < 0.05
     assert abs(r["report"]["U"] / peak_ref - 1) < 5e-3
