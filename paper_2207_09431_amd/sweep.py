@@ -18,14 +18,15 @@ from . import drag, inputs
 from .pflbm import PflbmError, Solver
 
 
-def run_sweep(cases: list, max_steps: int, every: int = 1000) -> list:
+def run_sweep(cases: list, max_steps: int, every: int = 1000, solver_factory=Solver) -> list:
     """Advances all `cases` (single-bubble cases, component 0 the gas) in one
     batched solver for up to `max_steps` steps, sampling the bubble
     diagnostics every `every` steps, and returns per case the samples and the
     report at the terminal sample (None when the case became non-finite or
     never peaked), and why sampling ended ("max_steps", "top_wall" or
-    "nonfinite by step N")."""
-    s = Solver([c["params"] for c in cases])
+    "nonfinite by step N").  `solver_factory` builds the batched solver
+    from the list of parameter blocks (the GPU Solver)."""
+    s = solver_factory([c["params"] for c in cases])
     for i, c in enumerate(cases):
         s.init_fields(i, c["C"], c.get("u"), c.get("p"))
     samples = [[] for _ in cases]
@@ -67,7 +68,7 @@ def run_sweep(cases: list, max_steps: int, every: int = 1000) -> list:
     # fraction of the case that peaked there
     order = sorted((r["peak_step"], i) for i, r in enumerate(out) if "peak_step" in r)
     if order:
-        s2 = Solver([c["params"] for c in cases])
+        s2 = solver_factory([c["params"] for c in cases])
         for i, c in enumerate(cases):
             s2.init_fields(i, c["C"], c.get("u"), c.get("p"))
         at = 0
