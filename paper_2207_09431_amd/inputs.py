@@ -254,14 +254,17 @@ def shear_thinning_sweep(density_ratio: float = 800.0, nx: int = 200, ny: int = 
     return out
 
 
-def three_component(variable_mobility: int = 0, nx: int = 256, ny: int = 512) -> dict:
+def three_component(variable_mobility: int = 0, nx: int = 256, ny: int = 512,
+                    density_ratio: float = 1000.0) -> dict:
     """Three components: C1 bubble R=40 at (128,160), C2 bubble R=25 at
     (128,330) above it, liquid C3 power law n=0.7, K=0.1, both dispersed
-    phases rho = 1e-3, nu = 1/6, sigma_ij = 1e-4, Lambda = 0."""
+    phases rho = 1/density_ratio (1e-3 by default), nu = 1/6,
+    sigma_ij = 1e-4, Lambda = 0; g from the gas-Mach rule at ratio 1000."""
     prm = default_params(nx, ny)
     sx, sy = nx / 256.0, ny / 512.0
     g = gravity_for_gas_mach(40.0, 1000.0, 0.01)
-    prm.update(n_h=2, rho=[1e-3, 1e-3, 1.0], nu=[1.0 / 6.0, 1.0 / 6.0, 1.0], powerlaw_comp=2,
+    rg = 1.0 / density_ratio
+    prm.update(n_h=2, rho=[rg, rg, 1.0], nu=[1.0 / 6.0, 1.0 / 6.0, 1.0], powerlaw_comp=2,
                K=0.1, n=0.7, nu_min=1e-4, nu_max=1.0, variable_mobility=variable_mobility,
                sigma12=1e-4, sigma13=1e-4, sigma23=1e-4, g=g)
     s = min(sx, sy)
