@@ -82,6 +82,17 @@ def li_terminal_velocity(d: float, g: float, rho_l: float, rho_g: float, k: floa
     return math.sqrt(lo * hi)
 
 
+def dimensionless_velocity(U: float, g: float, d: float) -> float:
+    """Rise velocity scaled by sqrt(g d) (Sec. 4.2)."""
+    return U / math.sqrt(g * d)
+
+
+def dimensionless_height(y: float, L: float) -> float:
+    """Centroid height scaled by the domain height 2L of the L x 2L box
+    (Sec. 4.2)."""
+    return y / (2.0 * L)
+
+
 def equivalent_diameter(area: float) -> float:
     """Diameter of the circle of the given area (the two-dimensional form of
     the paper's volume-equivalent diameter)."""
@@ -126,8 +137,9 @@ def bubble_report(diag, phi: np.ndarray, rho_l: float, rho_g: float, g: float, s
     centroid reduction (sum C, sum of C above 1/2, x_c, y_c, mean u_x, mean
     u_y; Eqs. (43)-(44)) and its gas-fraction field: U (the mean rise
     velocity unless given), d_e, E, Re, Eo, Mo, the drag coefficient of the
-    force balance and the correlation's drag coefficient and terminal
-    velocity at the measured E."""
+    force balance, the correlation's drag coefficient and terminal velocity
+    at the measured E, and the scaled velocity U / sqrt(g d_e) and height
+    y_c / (2L) of Sec. 4.2 (L the lattice width)."""
     mass, _, xc, yc, _, uy = (float(v) for v in diag)
     U = uy if U is None else float(U)
     de = equivalent_diameter(mass)
@@ -141,4 +153,6 @@ def bubble_report(diag, phi: np.ndarray, rho_l: float, rho_g: float, g: float, s
         "C_D": drag_coefficient(de, g, rho_l, rho_g, U),
         "C_D_li": li_drag_coefficient(Re, n, shape["E"]),
         "U_li": li_terminal_velocity(de, g, rho_l, rho_g, k, n, shape["E"]),
+        "U_star": dimensionless_velocity(U, g, de),
+        "y_star": dimensionless_height(yc, phi.shape[1]),
     }

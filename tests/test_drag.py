@@ -127,3 +127,16 @@ def test_sweep_recipe_is_table5():
         assert prm["rho"][2] / prm["rho"][0] == pytest.approx(800.0)
         assert c["C"].shape == (1, 400, 200) and c["C"][0, 120, 100] > 0.99
         assert c["C"][0, 120, 100 + 27] < 0.5 < c["C"][0, 120, 100 + 24]
+
+
+def test_dimensionless_velocity_and_height():
+    """Sec. 4.2 scales U by sqrt(g d) and the centroid height by 2L; the
+    report carries both (L = the lattice width of the L x 2L box)."""
+    assert drag.dimensionless_velocity(2e-3, 1e-6, 40.0) == pytest.approx(2e-3 / math.sqrt(4e-5), rel=1e-15)
+    assert drag.dimensionless_height(120.0, 200.0) == 0.3
+    case = inputs.shear_thinning_sweep(density_ratio=200.0)[3]
+    prm = case["params"]
+    phi = case["C"][0]
+    rep = drag.bubble_report((phi.sum(), 0.0, 100.0, 120.0, 0.0, 7e-4), phi, 1.0, 1 / 200, prm["g"],
+                             prm["sigma13"], prm["K"], prm["n"])
+    assert rep["y_star"] == pytest.approx(0.3) and rep["U_star"] == pytest.approx(7e-4 / math.sqrt(2e-7 * rep["d_e"]))
