@@ -1,0 +1,29 @@
+"""The stored oracle records in tests/golden come from the oracle as it
+stands: the first sample of the shear-thinning terminal-velocity record
+(1,000 steps of the 200 x 400 case) is recomputed here and must agree to
+rounding.  (The other record's first sample needs 8,000 steps of a
+128 x 512 case, minutes on the CPU; its script is the same shape.)"""
+import json
+import os
+
+import pytest
+
+from oracle.pfo import Oracle
+from paper_2207_09431_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_sweep_record_first_sample_recomputes():
+    with open(os.path.join(GOLDEN, "sweep_case4_terminal.json")) as f:
+        rec = json.load(f)
+    first = rec["samples"][0]
+    case = inputs.shear_thinning_sweep(density_ratio=200.0)[3]
+    assert rec["case"] == case["name"]
+    o = Oracle(case["params"])
+    o.init_fields(case["C"], case["u"], case["p"])
+    o.step(first["step"])
+    mass, _, _, yc, _, uy = o.centroid(0)
+    assert uy == pytest.approx(first["V_y"], rel=1e-9)
+    assert yc == pytest.approx(first["y_c"], rel=1e-12)
+    assert mass == pytest.approx(first["mass"], rel=1e-12)
