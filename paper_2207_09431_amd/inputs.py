@@ -233,15 +233,26 @@ TABLE5_FLUIDS = ((0.5, 1e-4, 5e-7, 2.61e-6), (0.5, 1e-4, 5e-7, 2.61e-5), (0.5, 2
                  (0.6, 5e-4, 2e-7, 2.61e-5), (0.63, 5e-4, 2e-7, 2.61e-5), (0.8, 1e-2, 5e-7, 2.61e-5))
 
 
-def shear_thinning_sweep(density_ratio: float = 800.0, nx: int = 200, ny: int = 400) -> list:
-    """The six bubbles of Table 5: d = nx/4 at (nx/2, 0.6 nx) (Eq. (42)) in a
-    power-law liquid (rho_l = 1) with the printed n, k, g and sigma; gas
-    nu = c_s^2 * 0.5 (tau_d = 0.5), nu in [1e-4, 1], constant mobility
+def grid_scaled(n: float, k: float, g: float, sigma: float, f: float):
+    """Power-law consistency, gravity and surface tension on a lattice f times
+    finer with the same Re, Eo and Mo (Eqs. (38)-(40)): lattice velocities
+    scale by 1/f and lengths by f, so k * f^(2n-2), g / f^3, sigma / f
+    (for n = 0.5 this is the progression of Table 4's grids)."""
+    return k * f ** (2.0 * n - 2.0), g / f ** 3, sigma / f
+
+
+def shear_thinning_sweep(density_ratio: float = 800.0, scale: int = 1) -> list:
+    """The six bubbles of Table 5: d = L/4 at (L/2, 0.6 L) (Eq. (42)) on an
+    L x 2L lattice, L = 200 * scale, in a power-law liquid (rho_l = 1) with
+    the printed n, k, g and sigma (scaled by `grid_scaled` when scale > 1);
+    gas nu = c_s^2 * 0.5 (tau_d = 0.5), nu in [1e-4, 1], constant mobility
     xi/300, the bubble started at its rest pressure.  The paper's density
     ratio is 800."""
     out = []
+    nx, ny = 200 * scale, 400 * scale
     d = nx / 4.0
-    for i, (n, k, g, sigma) in enumerate(TABLE5_FLUIDS):
+    for i, (n, k0, g0, sigma0) in enumerate(TABLE5_FLUIDS):
+        k, g, sigma = grid_scaled(n, k0, g0, sigma0, scale)
         prm = default_params(nx, ny)
         rg = 1.0 / density_ratio
         prm.update(rho=[rg, rg, 1.0], nu=[1.0 / 6.0, 1.0 / 6.0, 1.0], powerlaw_comp=2,

@@ -89,8 +89,10 @@ def main(argv=None) -> int:
     ap.add_argument("--cases", default="1,2,3,4,5,6", help="Table 5 cases to run (1-based)")
     ap.add_argument("--steps", type=int, default=60000)
     ap.add_argument("--every", type=int, default=1000)
+    ap.add_argument("--scale", type=int, default=1,
+                    help="lattice f times finer than 200 x 400 at the same Re, Eo and Mo")
     a = ap.parse_args(argv)
-    all_cases = inputs.shear_thinning_sweep(density_ratio=a.ratio)
+    all_cases = inputs.shear_thinning_sweep(density_ratio=a.ratio, scale=a.scale)
     pick = [int(x) - 1 for x in a.cases.split(",")]
     for r in run_sweep([all_cases[i] for i in pick], a.steps, a.every):
         r = dict(r)

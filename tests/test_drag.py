@@ -140,3 +140,32 @@ def test_dimensionless_velocity_and_height():
     rep = drag.bubble_report((phi.sum(), 0.0, 100.0, 120.0, 0.0, 7e-4), phi, 1.0, 1 / 200, prm["g"],
                              prm["sigma13"], prm["K"], prm["n"])
     assert rep["y_star"] == pytest.approx(0.3) and rep["U_star"] == pytest.approx(7e-4 / math.sqrt(2e-7 * rep["d_e"]))
+
+
+# Table 4: grids 1-4 (L = 50, 100, 200, 400), n = 0.5: k, g, sigma as printed
+TABLE4 = [(2e-4, 8e-6, 1.044e-4), (1e-4, 1e-6, 5.22e-5), (5e-5, 1.25e-7, 2.61e-5), (2.5e-5, 1.56e-8, 1.3e-5)]
+
+
+def test_grid_scaling_reproduces_table4():
+    """The Re/Eo/Mo-preserving scaling gives Table 4's progression from grid 1
+    to grids 2-4 (n = 0.5) to the printed digits."""
+    k1, g1, s1 = TABLE4[0]
+    for j, (k, g, s) in enumerate(TABLE4[1:], start=1):
+        kk, gg, ss = inputs.grid_scaled(0.5, k1, g1, s1, 2 ** j)
+        assert kk == pytest.approx(k, rel=1e-12)
+        assert gg == pytest.approx(g, rel=3e-3)          # 1.5625e-8 printed as 1.56e-8
+        assert ss == pytest.approx(s, rel=4e-3)          # 1.305e-5 printed as 1.3e-5
+
+
+@pytest.mark.parametrize("n", [0.5, 0.6, 0.8, 1.0])
+def test_grid_scaling_keeps_re_eo_mo(n):
+    """With lattice velocity U/f and diameter f d, the scaled k, g, sigma leave
+    Re, Eo and Mo of Eqs. (38)-(40) unchanged (and U / sqrt(g d) too)."""
+    k, g, s, U, d, f = 5e-4, 2e-7, 2.61e-5, 7.8e-4, 50.0, 3
+    kk, gg, ss = inputs.grid_scaled(n, k, g, s, f)
+    assert drag.reynolds(1.0, U / f, d * f, kk, n) == pytest.approx(drag.reynolds(1.0, U, d, k, n), rel=1e-12)
+    assert drag.eotvos(1.0, gg, d * f, ss) == pytest.approx(drag.eotvos(1.0, g, d, s), rel=1e-12)
+    assert drag.morton(gg, 1.0, 1.0, ss, kk, U / f, d * f, n) == pytest.approx(drag.morton(g, 1.0, 1.0, s, k, U, d, n), rel=1e-12)
+    assert drag.dimensionless_velocity(U / f, gg, d * f) == pytest.approx(drag.dimensionless_velocity(U, g, d), rel=1e-12)
+    big = inputs.shear_thinning_sweep(scale=2)[3]
+    assert big["C"].shape == (1, 800, 400) and big["C"][0, 240, 200] > 0.99
