@@ -151,7 +151,7 @@ def cpu_baseline(seconds):
 
 
 def small_configs(torch, Solver, inputs, steps, warmup):
-    """The smaller configurations (cache-resident, launch-bound): the 64 x 128
+    """The smaller configurations (cache-resident, bound by the latency of one tile step): the 64 x 128
     rising bubble, a 200 x 400 power-law bubble (d = 40) and the 256 x 512
     three-component case; plain launches and 10-step hipGraph replay."""
     out = {}
