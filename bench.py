@@ -151,9 +151,10 @@ def cpu_baseline(seconds):
 
 
 def small_configs(torch, Solver, inputs, steps, warmup):
-    """The smaller configurations (cache-resident, bound by the latency of one tile step): the 64 x 128
-    rising bubble, a 200 x 400 power-law bubble (d = 40) and the 256 x 512
-    three-component case; plain launches and 10-step hipGraph replay."""
+    """The smaller configurations (cache-resident, bound by the latency of one
+    tile's step): the 64 x 128 rising bubble, a 200 x 400 power-law bubble
+    (d = 40) and the 256 x 512 three-component case; plain launches and
+    10-step hipGraph replay."""
     out = {}
     for name, case in (("rising_bubble_64x128", inputs.rising_bubble_small()),
                        ("powerlaw_bubble_200x400", inputs.powerlaw_bubble(n=0.8, d=40.0)),
