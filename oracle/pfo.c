@@ -77,11 +77,14 @@
 #include "pfo.h"
 
 /* Per-node loops are split over rows with OpenMP when the library is built
- * with it.  Each node is computed by one thread with the same operations, so
- * the results do not depend on the thread count.  (Testing only: speed.) */
+ * with it, for domains of 4096 nodes or more (smaller ones run on the calling
+ * thread: starting a parallel region costs more than such a loop).  Each
+ * node is computed by one thread with the same operations, so the results do
+ * not depend on the thread count.  (Testing only: speed.)  OMP_FOR is used
+ * only where the context `c` is in scope. */
 #ifdef _OPENMP
 #include <omp.h>
-#define OMP_FOR _Pragma("omp parallel for schedule(static)")
+#define OMP_FOR _Pragma("omp parallel for schedule(static) if(c->n >= 4096)")
 #else
 #define OMP_FOR
 #endif
@@ -751,9 +754,14 @@ int pfo_fields(pfo_ctx *c, double *out) {
 }
 
 /* Mass, mass of cells with C>0.5, centroid and mean velocity of component comp
- * (Sec. 3.1 for the thresholded mass; Sec. 4.2, Eqs. (43)-(44)). */
+ * (Sec. 3.1 for the thresholded mass; Sec. 4.2, Eqs. (43)-(44)).  The
+ * centroid is the plain C-weighted mean of the node coordinates: a bubble
+ * that straddles the periodic seam in x reports a mean between its two
+ * halves.  Returns -1 for component 1 (C_2) when only one phase field is
+ * carried, -4 when the component's mass is zero or a sum is not finite. */
 int pfo_bubble_centroid_velocity(pfo_ctx *c, int comp, double out[6]) {
     if (!c || !out || comp < 0 || comp > 2) return -1;
+    if (comp == 1 && c->p.n_h == 1) return -1;
     macro_from_state(c);
     int nx = c->nx, ny = c->ny, n = c->n;
     double m = 0.0, mh = 0.0, sx = 0.0, sy = 0.0, su = 0.0, sv = 0.0;
@@ -768,6 +776,9 @@ int pfo_bubble_centroid_velocity(pfo_ctx *c, int comp, double out[6]) {
             su += cg * c->u[q];
             sv += cg * c->u[n + q];
         }
+    if (!(m != 0.0) || !isfinite(m) || !isfinite(mh) || !isfinite(sx) || !isfinite(sy) || !isfinite(su) ||
+        !isfinite(sv))
+        return -4;
     out[0] = m; out[1] = mh;
     out[2] = sx / m; out[3] = sy / m; out[4] = su / m; out[5] = sv / m;
     return 0;

@@ -52,6 +52,7 @@ int pfo_init_fields(pfo_ctx *c, const double *C, const double *u, const double *
 int pfo_step(pfo_ctx *c, int64_t nsteps);
 int pfo_macroscopic(pfo_ctx *c, double *rho, double *u, double *p, double *phi);
 int pfo_fields(pfo_ctx *c, double *out);
+/* -1: bad comp (1 with n_h = 1); -4: zero mass or a non-finite sum */
 int pfo_bubble_centroid_velocity(pfo_ctx *c, int comp, double out[6]);
 size_t pfo_state_doubles(const pfo_ctx *c);
 int pfo_get_state(const pfo_ctx *c, double *dst);

@@ -1,6 +1,8 @@
 """Mutation check of the oracle's pins, run by hand (not collected by pytest):
 
-    python tests/mutation_check.py
+    python tests/mutation_check.py [substring ...]
+
+(with substrings, only the mutations whose description contains one of them run).
 
 Each mutation plants one plausible mistake in a copy of oracle/pfo.c (a
 dropped term, a wrong sign or factor, a wrong index), builds it with the
@@ -63,6 +65,36 @@ MUTATIONS = [
      [("1.0 / (P->tau_h + 0.5)", "1.0 / P->tau_h")]),
     ("gradient part of the variable-mobility source dropped",
      [("v += c->p.D0 / S[i] * (ax", "v += 0.0 * c->p.D0 / S[i] * (ax")]),
+    ("ternary term of the bulk energy with Sigma_1 and Sigma_2 swapped",
+     [("c1 * c2 * c3 * (S[0] * c1 + S[1] * c2 + S[2] * c3)", "c1 * c2 * c3 * (S[1] * c1 + S[0] * c2 + S[2] * c3)")]),
+    ("six-fold Lambda term of the bulk energy missing a square",
+     [("+ p->Lambda * c1 * c1 * c2 * c2 * c3 * c3;", "+ p->Lambda * c1 * c2 * c2 * c3 * c3;")]),
+    ("derivative of the bulk energy along C_2 with Sigma_1 in its ternary term",
+     [("c1 * c3 * sc + c1 * c2 * c3 * S[1]", "c1 * c3 * sc + c1 * c2 * c3 * S[0]")]),
+    ("derivative of the bulk energy along C_1 with half its Lambda term",
+     [("+ 2.0 * p->Lambda * c1 * c2 * c2 * c3 * c3;", "+ p->Lambda * c1 * c2 * c2 * c3 * c3;")]),
+    ("second component's hbar takes the first component's diffusion source",
+     [("double difi = c->dif[i * n + q];", "double difi = c->dif[q];")]),
+    ("second component's receiving-node diffusion half from the first component",
+     [("+ 0.5 * c->dif[i * n + q] * G;", "+ 0.5 * c->dif[q] * G;")]),
+    ("density of component 2 taken from component 1's",
+     [("p->rho[1] * clip01(c2)", "p->rho[0] * clip01(c2)")]),
+    ("ternary term with Sigma_1 and Sigma_2 swapped in the energy and its derivatives alike",
+     [("c1 * c2 * c3 * (S[0] * c1 + S[1] * c2 + S[2] * c3)", "c1 * c2 * c3 * (S[1] * c1 + S[0] * c2 + S[2] * c3)"),
+      ("double sc = S[0] * c1 + S[1] * c2 + S[2] * c3;", "double sc = S[1] * c1 + S[0] * c2 + S[2] * c3;"),
+      ("+ c2 * c3 * sc + c1 * c2 * c3 * S[0]", "+ c2 * c3 * sc + c1 * c2 * c3 * S[1]"),
+      ("+ c1 * c3 * sc + c1 * c2 * c3 * S[1]", "+ c1 * c3 * sc + c1 * c2 * c3 * S[0]")]),
+    ("Lambda term read as Lambda C1 C2 C3 in the energy and its derivatives alike",
+     [("+ p->Lambda * c1 * c1 * c2 * c2 * c3 * c3;", "+ p->Lambda * c1 * c2 * c3;"),
+      ("+ 2.0 * p->Lambda * c1 * c2 * c2 * c3 * c3;", "+ p->Lambda * c2 * c3;"),
+      ("+ 2.0 * p->Lambda * c1 * c1 * c2 * c3 * c3;", "+ p->Lambda * c1 * c3;"),
+      ("+ 2.0 * p->Lambda * c1 * c1 * c2 * c2 * c3;", "+ p->Lambda * c1 * c2;")]),
+    ("mass above one half counts cells instead of summing C",
+     [("if (cg > 0.5) mh += cg;", "if (cg > 0.5) mh += 1.0;")]),
+    ("mean velocity weighted by 1 instead of C",
+     [("su += cg * c->u[q];", "su += c->u[q];")]),
+    ("centroid height weighted by the clipped C",
+     [("sy += cg * y;", "sy += (cg < 0.0 ? 0.0 : (cg > 1.0 ? 1.0 : cg)) * y;")]),
 ]
 
 # Mistakes in parts that no closed form or invariant reaches (their parity is
@@ -81,9 +113,15 @@ def build(src_text, tmp):
     return lib
 
 
+# pin files in the order they run: the quick ones first, since the run stops
+# at the first failing pin
+FAST_FIRST = ("thermo", "stencils", "lattice", "diagnostics", "dynamics", "interface", "locality", "mobility")
+
+
 def run_pins(lib):
-    tests = sorted(os.path.join(ROOT, "tests", f) for f in os.listdir(os.path.join(ROOT, "tests"))
-                   if f.startswith("test_oracle_") and f.endswith(".py"))
+    names = [f for f in os.listdir(os.path.join(ROOT, "tests")) if f.startswith("test_oracle_") and f.endswith(".py")]
+    rank = lambda f: next((i for i, k in enumerate(FAST_FIRST) if f == f"test_oracle_{k}.py"), len(FAST_FIRST))
+    tests = [os.path.join(ROOT, "tests", f) for f in sorted(names, key=lambda f: (rank(f), f))]
     env = dict(os.environ, PFO_LIBRARY=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *tests],
                        cwd=ROOT, env=env, capture_output=True, text=True)
@@ -94,7 +132,10 @@ def run_pins(lib):
 def main():
     src = open(os.path.join(ROOT, "oracle", "pfo.c")).read()
     survivors = 0
+    only = sys.argv[1:]          # run only the mutations whose description contains one of these
     for what, edits in MUTATIONS + UNPINNED:
+        if only and not any(o in what for o in only):
+            continue
         pinned = (what, edits) in MUTATIONS
         text = src
         for old, new in edits:

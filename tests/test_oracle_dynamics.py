@@ -164,3 +164,57 @@ def test_accelerated_slab_moves_with_the_fluid():
     x0 = centroid()
     o.step(N)
     assert abs((centroid() - x0) / (0.5 * f * N * N) - 1) < 5e-3
+
+
+def _ternary_touching(nx=48, ny=64, swap=False):
+    """Two dispersed components whose rims overlap (C1 C2 up to ~0.03, all
+    three components present there) in a power-law liquid; every pairwise
+    parameter differs between components 1 and 2.  With swap=True the labels
+    1 and 2 are exchanged: rho_1 <-> rho_2, nu_1 <-> nu_2,
+    sigma_13 <-> sigma_23 (sigma_12 stays), and the two fields."""
+    prm = inputs.default_params(nx, ny)
+    prm.update(n_h=2, rho=[0.1, 0.2, 1.0], nu=[0.1, 0.15, 1.0 / 6.0], powerlaw_comp=2, K=0.05, n=0.7,
+               variable_mobility=0, sigma12=1e-3, sigma13=1.2e-3, sigma23=0.9e-3, Lambda=2e-3, g=2e-6,
+               D0=0.02)
+    a = inputs.bubble_field(nx, ny, [(14.0, 20.0, 8.0)], prm["xi"])
+    b = inputs.bubble_field(nx, ny, [(26.0, 34.0, 7.0)], prm["xi"])
+    C = np.stack([a, b])
+    if swap:
+        prm.update(rho=[0.2, 0.1, 1.0], nu=[0.15, 0.1, 1.0 / 6.0], sigma13=0.9e-3, sigma23=1.2e-3)
+        C = C[::-1].copy()
+    return prm, C, inputs.velocity_noise(nx, ny, 3, 1e-4)
+
+
+def test_component_exchange_symmetry():
+    """Sec. 2.1-2.2 treat the carried components 1 and 2 alike: relabelling
+    them (fields and every per-component parameter) must permute C_1 and C_2
+    and leave u and p unchanged, up to the rounding of sums taken in another
+    order.  A term that uses the wrong component's field, density, viscosity
+    or capillary coefficient breaks the permutation at first order."""
+    pA, CA, u = _ternary_touching()
+    pB, CB, _ = _ternary_touching(swap=True)
+    oA, oB = Oracle(pA), Oracle(pB)
+    oA.init_fields(CA, u)
+    oB.init_fields(CB, u)
+    oA.step(120)
+    oB.step(120)
+    A, B = oA.macroscopic(), oB.macroscopic()
+    assert (A["phi"][0] * A["phi"][1]).max() > 0.02          # the rims still overlap
+    assert np.abs(A["phi"][0] - B["phi"][1]).max() < 1e-14
+    assert np.abs(A["phi"][1] - B["phi"][0]).max() < 1e-14
+    assert np.abs(A["u"] - B["u"]).max() < 1e-12 * np.abs(A["u"]).max()
+    assert np.abs(A["p"] - B["p"]).max() < 1e-12 * np.abs(A["p"]).max()
+
+
+def test_three_component_mass_exact_with_central_hbar_forcing():
+    """With central differences in the hbar forcing (switch hforce_mode=1)
+    the sum over directions of every source term of Eq. (18) telescopes, so
+    the mass of each carried component and of the liquid is conserved to
+    round-off also where all three components meet."""
+    prm, C, u = _ternary_touching()
+    o = Oracle(dict(prm, hforce_mode=1))
+    o.init_fields(C, u)
+    m0 = [o.centroid(k)[0] for k in range(3)]
+    o.step(150)
+    for k in range(3):
+        assert abs(o.centroid(k)[0] / m0[k] - 1.0) < 5e-14, k

@@ -94,3 +94,79 @@ def test_tanh_profile_is_continuum_equilibrium():
         cpp = -(4.0 / xi ** 2) * t * (1 - t * t)    # d^2/dz^2 of 1/2 + 1/2 tanh(2z/xi)
         mu = pfo.chem_potential(p, [c, 0.0, 1 - c], [cpp, 0.0, -cpp])
         assert abs(mu[0]) < 1e-17
+
+
+def _energy_sum_form(S, lam, c):
+    """E0 written per component: sum_i (Sigma_i / 2) C_i^2 (1 - C_i)^2 +
+    Lambda C1^2 C2^2 C3^2.  Equal to Eq. (3) whenever C1 + C2 + C3 = 1
+    (expand (1 - C_i)^2 = (C_j + C_k)^2 and use Sigma_i + Sigma_j =
+    2 sigma_ij); it shares no term-by-term structure with the pairwise form."""
+    c = np.asarray(c, dtype=np.float64)
+    return float(sum(0.5 * S[i] * c[i] ** 2 * (1.0 - c[i]) ** 2 for i in range(3))
+                 + lam * (c[0] * c[1] * c[2]) ** 2)
+
+
+def _random_ternary(rng):
+    s = rng.uniform(5e-4, 2e-3, 3)
+    s = s + 0.5 * s.max()                 # every Sigma_i > 0
+    S = np.array([s[0] + s[1] - s[2], s[0] + s[2] - s[1], s[1] + s[2] - s[0]])
+    return s, S, rng.uniform(1e-4, 3e-3)
+
+
+def test_ternary_energy_equals_per_component_form():
+    """Interior of the ternary bulk energy (Sec. 2.1, Eq. (3) under the
+    constraint Eq. (1)): the C1 C2 C3 (Sigma_1 C1 + Sigma_2 C2 + Sigma_3 C3)
+    and Lambda C1^2 C2^2 C3^2 terms are checked against the per-component
+    form on states with all three components present, Lambda > 0."""
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        s, S, lam = _random_ternary(rng)
+        p = params(s[0], s[1], s[2], lam)
+        c = rng.dirichlet([1.5, 1.5, 1.5])
+        c[2] = 1.0 - c[0] - c[1]
+        ref = _energy_sum_form(S, lam, c)
+        assert abs(pfo.bulk_energy(p, *c) - ref) <= 1e-14 * abs(ref) + 1e-20
+
+
+def test_ternary_potential_from_per_component_energy():
+    """Bulk chemical potentials (Sec. 2.1, Eq. (5) with lap C = 0):
+    dE0/dC_i - dE0/dC_j is the derivative of E0 along e_i - e_j, a direction
+    inside the plane C1 + C2 + C3 = 1, so it can be taken by central finite
+    differences of the per-component form alone; then
+    mu_i = (4 Sigma_T / xi) sum_{j != i} (that derivative) / Sigma_j with
+    3 / Sigma_T = sum 1 / Sigma_i (Eq. (7))."""
+    rng = np.random.default_rng(12)
+    xi = 4.0
+    for _ in range(100):
+        s, S, lam = _random_ternary(rng)
+        p = params(s[0], s[1], s[2], lam, xi)
+        c = rng.dirichlet([2.0, 2.0, 2.0])
+        ST = 3.0 / (1.0 / S).sum()
+        h = 1e-5
+        ref = np.zeros(3)
+        for i in range(3):
+            for j in range(3):
+                if j == i:
+                    continue
+                e = np.zeros(3)
+                e[i], e[j] = 1.0, -1.0
+                dij = (_energy_sum_form(S, lam, c + h * e) - _energy_sum_form(S, lam, c - h * e)) / (2 * h)
+                ref[i] += 4.0 * ST / xi * dij / S[j]
+        mu = pfo.chem_potential(p, c, [0.0, 0.0, 0.0])
+        scale = np.abs(ref).max()
+        assert np.abs(mu - ref).max() < 1e-8 * scale, (mu, ref)
+
+
+def test_ternary_gradient_term_per_component():
+    """The gradient part of Eq. (5) is -(3/4) xi Sigma_i lap C_i for each
+    component on its own: with the bulk part removed (a pure state, where
+    E0 and all its derivatives vanish) mu_i carries only that term."""
+    rng = np.random.default_rng(13)
+    for _ in range(20):
+        s, S, lam = _random_ternary(rng)
+        xi = rng.uniform(3.0, 5.0)
+        p = params(s[0], s[1], s[2], lam, xi)
+        lap = rng.normal(0, 1e-2, 3)
+        lap[2] = -lap[0] - lap[1]
+        mu = pfo.chem_potential(p, [0.0, 0.0, 1.0], lap)
+        assert np.abs(mu + 0.75 * xi * S * lap).max() < 1e-16
