@@ -118,9 +118,11 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
 /*
  * Initial state of one case from host fields (Sec. 4.2: quiescent start,
  * tanh interface of Eq. (42) supplied by the caller): C holds n_h planes,
- * u two planes (u_x then u_y) or NULL for zero, p one plane or NULL for zero.
- * Populations start at their equilibria (Eqs. (16), (20)) and tau at its
- * zero-shear value.  Errors: NONFINITE for a non-finite input.
+ * u two planes (u_x then u_y) or NULL for zero, p one plane or NULL for zero,
+ * each plane nx * ny doubles (the ABI reads exactly that many; the caller
+ * guarantees the sizes).  Populations start at their equilibria
+ * (Eqs. (16), (20)) and tau at its zero-shear value; the case's non-finite
+ * flag is cleared.  Synchronises.  Errors: NONFINITE for a non-finite input.
  */
 int32_t pflbm_init_fields(pflbm_ctx* ctx, int32_t case_id, const double* C, const double* u,
                           const double* p);
@@ -145,14 +147,44 @@ int32_t pflbm_macroscopic(pflbm_ctx* ctx, int32_t case_id, float* d_rho, float* 
  * Bubble diagnostics of component `comp` (0..2) of one case, summed in
  * float64 on the device (Sec. 3.1 thresholded mass; Sec. 4.2,
  * Eqs. (43)-(44)): out = { sum C, sum of C over cells with C > 0.5,
- * centroid x, centroid y, mean u_x, mean u_y } with weights C.  Synchronises
- * the stream.  Errors: NONFINITE when a summed quantity is not finite.
+ * centroid x, centroid y, mean u_x, mean u_y } with weights C (unclipped;
+ * component 2 is C_3 = 1 - C_1 - C_2).  The centroid is the plain C-weighted
+ * mean of the node coordinates (x in [0, nx), y in [0, ny)): a bubble that
+ * straddles the periodic seam in x reports a mean between its two halves.
+ * Synchronises the stream.  Errors: INVALID_ARG for comp = 1 when n_h = 1
+ * (C_2 is not carried); NONFINITE when the case's state or a summed quantity
+ * is not finite (the case's sticky flag, below), or when the component's
+ * mass is zero (no centroid).
  */
 int32_t pflbm_bubble_centroid_velocity(pflbm_ctx* ctx, int32_t case_id, int32_t comp, double out[6]);
 
 /*
+ * Divergence detection (sticky NONFINITE).  Every case carries a device flag
+ * that the once-per-call kernels (pflbm_macroscopic,
+ * pflbm_bubble_centroid_velocity, pflbm_export_populations and the scan
+ * below) set when they meet a non-finite value in the state or in the fields
+ * derived from it.  A synchronising call that finds a case's flag set makes
+ * it sticky on the host: from then on pflbm_bubble_centroid_velocity of that
+ * case, pflbm_check_state and pflbm_autotune return NONFINITE, until
+ * pflbm_init_fields (that case) or pflbm_set_state (every case) clears it.
+ * pflbm_step stays asynchronous and does not test the flag (cases of a batch
+ * are independent: the others can still be advanced).
+ *
+ * pflbm_check_state scans the complete state of every case (one read of
+ * it), synchronises, and returns NONFINITE if any case is flagged, OK
+ * otherwise; STATE before every case has been initialised.
+ * pflbm_case_nonfinite returns 1 if case_id is flagged on the host (as of
+ * the last synchronising call), 0 if not, INVALID_ARG for a bad case_id;
+ * it does not touch the device.
+ */
+int32_t pflbm_check_state(pflbm_ctx* ctx);
+int32_t pflbm_case_nonfinite(const pflbm_ctx* ctx, int32_t case_id);
+
+/*
  * Checkpoint: copies the complete state of every case (device to device)
  * into/out of a caller buffer of pflbm_state_bytes bytes.  Asynchronous.
+ * pflbm_set_state clears every case's non-finite flag (the restored state
+ * is scanned again by the next diagnostic call).
  */
 size_t pflbm_state_bytes(const pflbm_ctx* ctx);
 int32_t pflbm_get_state(pflbm_ctx* ctx, void* d_dst, size_t bytes);
@@ -181,7 +213,8 @@ int32_t pflbm_set_variant(pflbm_ctx* ctx, int32_t index);
  * timed launch recomputes the same step into the spare buffer).  `best`
  * receives the chosen index; `ms_per_variant` (NULL or pflbm_num_variants
  * floats) receives the mean milliseconds per step, -1 for a variant that does
- * not apply.  Synchronises the stream.  Errors: STATE before init_fields.
+ * not apply.  Synchronises the stream.  Errors: STATE before init_fields;
+ * NONFINITE (after tuning) when a case is flagged non-finite.
  */
 int32_t pflbm_autotune(pflbm_ctx* ctx, int32_t steps, int32_t* best, float* ms_per_variant);
 

@@ -24,47 +24,52 @@ struct NodeStencil {
 };
 
 // Central-difference stencils of C_i and rho and the chemical potentials at
-// an in-domain node, from a C field given by `get(x, y, c1, c2)`.
+// an in-domain node, from a C field given by `get(x, y, c1, c2)`, in the
+// arithmetic of the step kernel's phase B: grad C_i from the float32-rounded
+// C_i, lap C_i from the float64 field (rounded once), rho from the float64
+// C_i, grad rho from the float32 rho of the neighbours.
 template <class Get>
 __device__ __forceinline__ NodeStencil stencil_at(const CaseDev& cd, int x, int y, Get get) {
     NodeStencil n;
-    double d1, d2;
-    get(x, y, d1, d2);
-    const float c1 = (float)d1, c2 = (float)d2;
-    n.c[0] = c1;
-    n.c[1] = c2;
-    n.rho = mix_rho(cd, d1, d2);
-    float sx[2] = {0.f, 0.f}, sy[2] = {0.f, 0.f}, sl[2] = {0.f, 0.f}, rx = 0.f, ry = 0.f;
+    double q1[9], q2[9];
+    float f1[9], f2[9], r[9];
 #pragma unroll
-    for (int a = 1; a < 9; ++a) {
-        double q1, q2, r1, r2;
-        get(wrap_x(x + Lat::ex[a], cd.nx), mirror_y(y + Lat::ey[a], cd.ny), q1, q2);
-        get(wrap_x(x - Lat::ex[a], cd.nx), mirror_y(y - Lat::ey[a], cd.ny), r1, r2);
-        const float p1 = (float)q1, p2 = (float)q2, m1 = (float)r1, m2 = (float)r2;
-        const float w = Lat::w[a];
-        sx[0] += w * Lat::ex[a] * (p1 - m1);
-        sy[0] += w * Lat::ey[a] * (p1 - m1);
-        sl[0] += w * ((p1 - c1) + (m1 - c1));
-        sx[1] += w * Lat::ex[a] * (p2 - m2);
-        sy[1] += w * Lat::ey[a] * (p2 - m2);
-        sl[1] += w * ((p2 - c2) + (m2 - c2));
-        const float dr = mix_rho(cd, q1, q2) - mix_rho(cd, r1, r2);
-        rx += w * Lat::ex[a] * dr;
-        ry += w * Lat::ey[a] * dr;
+    for (int a = 0; a < 9; ++a) {
+        get(wrap_x(x + Lat::ex[a], cd.nx), mirror_y(y + Lat::ey[a], cd.ny), q1[a], q2[a]);
+        f1[a] = (float)q1[a];
+        f2[a] = (float)q2[a];
+        r[a] = mix_rho(cd, q1[a], q2[a]);
     }
-    for (int i = 0; i < 2; ++i) {
-        n.gcx[i] = 1.5f * sx[i];
-        n.gcy[i] = 1.5f * sy[i];
-        n.lc[i] = 3.0f * sl[i];
+    n.c[0] = f1[0];
+    n.c[1] = f2[0];
+    n.rho = r[0];
+    cd_grad9(f1, n.gcx[0], n.gcy[0]);
+    n.lc[0] = cd_lap9_d(q1);
+    if (cd.n_h == 2) {
+        cd_grad9(f2, n.gcx[1], n.gcy[1]);
+        n.lc[1] = cd_lap9_d(q2);
+    } else {
+        n.gcx[1] = n.gcy[1] = n.lc[1] = 0.0f;
     }
-    n.grx = 1.5f * rx;
-    n.gry = 1.5f * ry;
-    if (cd.n_h == 1) chem_potential<1>(cd, d1, d2, n.lc[0], n.lc[1], n.mu);
-    else chem_potential<2>(cd, d1, d2, n.lc[0], n.lc[1], n.mu);
+    cd_grad9(r, n.grx, n.gry);
+    if (cd.n_h == 1) chem_potential<1>(cd, q1[0], q2[0], n.lc[0], n.lc[1], n.mu);
+    else chem_potential<2>(cd, q1[0], q2[0], n.lc[0], n.lc[1], n.mu);
     return n;
 }
 
-// rho, u, p of an in-domain node from the current state (Eqs. (23), (24)).
+// sum_k mu_k grad C_k + F_b with grad C_3 = -grad C_1 - grad C_2, in the
+// step kernel's order of operations.
+__device__ __forceinline__ void node_force(const CaseDev& cd, const NodeStencil& n, float& fx, float& fy) {
+    fx = (n.mu[0] - n.mu[2]) * n.gcx[0] + n.rho * cd.fx;
+    fy = (n.mu[0] - n.mu[2]) * n.gcy[0] - n.rho * cd.g;
+    if (cd.n_h == 2) {
+        fx += (n.mu[1] - n.mu[2]) * n.gcx[1];
+        fy += (n.mu[1] - n.mu[2]) * n.gcy[1];
+    }
+}
+
+// rho, u, p of an in-domain node from the current state (Eqs. (23), (24)),
+// rounded as in the step kernel.
 __device__ __forceinline__ void node_macro(const CaseDev& cd, int par, int x, int y, NodeStencil& n, float& ux,
                                            float& uy, float& p) {
     const double* C = cd.C[par];
@@ -72,15 +77,23 @@ __device__ __forceinline__ void node_macro(const CaseDev& cd, int par, int x, in
     const long long off = (long long)y * cd.pitch + x;
     float d[9];
     load_devs(cd, par, off, d);
-    const float s = (float)(cd.P[par][off] + pref_d(cd, y));
+    const double s = cd.P[par][off];
     const float jx = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
     const float jy = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
-    const float mu13 = n.mu[0] - n.mu[2], mu23 = n.mu[1] - n.mu[2];
-    const float fx = mu13 * n.gcx[0] + mu23 * n.gcx[1] + n.rho * cd.fx;
-    const float fy = mu13 * n.gcy[0] + mu23 * n.gcy[1] - n.rho * cd.g;
-    ux = (3.0f * jx + 0.5f * fx) / n.rho;
-    uy = (3.0f * jy + 0.5f * fy) / n.rho;
-    p = s + 0.5f * kCs2 * (ux * n.grx + uy * n.gry);
+    float fx, fy;
+    node_force(cd, n, fx, fy);
+    const float rr = rcp(n.rho);
+    ux = (3.0f * jx + 0.5f * fx) * rr;
+    uy = (3.0f * jy + 0.5f * fy) * rr;
+    // the step keeps p - p_ref; the reference is added back in float64
+    const float pr = (float)s + 0.5f * kCs2 * (ux * n.grx + uy * n.gry);
+    p = (float)((double)pr + pref_d(cd, y));
+}
+
+// Marks the case's non-finite flag: a plain per-lane global store of 1 by
+// every lane that found a non-finite value (all write the same word).
+__device__ __forceinline__ void mark_nonfinite(const CaseDev& cd, bool bad) {
+    if (bad) *cd.flag = 1u;
 }
 
 __global__ __launch_bounds__(kBlock) void init_kernel(const CaseDev* __restrict__ cdp, int par,
@@ -114,9 +127,8 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const CaseDev* __restrict_
         gpy *= 1.5f;
     }
     const float rho = st.rho;
-    const float mu13 = st.mu[0] - st.mu[2], mu23 = st.mu[1] - st.mu[2];
-    const float Fx = mu13 * st.gcx[0] + mu23 * st.gcx[1] + rho * cd.fx;
-    const float Fy = mu13 * st.gcy[0] + mu23 * st.gcy[1] - rho * cd.g;
+    float Fx, Fy;
+    node_force(cd, st, Fx, Fy);
     const float uu = ux * ux + uy * uy, ugr = ux * st.grx + uy * st.gry, uF = ux * Fx + uy * Fy;
     const float ps = 0.5f * kCs2 * ugr;                      // p - sum gbar_eq
     const float rc2 = rho * kCs2;
@@ -168,6 +180,7 @@ __global__ __launch_bounds__(kBlock) void macro_kernel(const CaseDev* __restrict
     NodeStencil st;
     float ux, uy, pp;
     node_macro(cd, par, x, y, st, ux, uy, pp);
+    mark_nonfinite(cd, !(isfinite(ux) && isfinite(uy) && isfinite(pp) && isfinite(st.c[0]) && isfinite(st.c[1])));
     if (rho) rho[q] = st.rho;
     if (u) { u[q] = ux; u[n + q] = uy; }
     if (p) p[q] = pp;
@@ -191,8 +204,44 @@ __global__ __launch_bounds__(kBlock) void export_kernel(const CaseDev* __restric
         out[a * n + q] = Lat::w[a] * s + da;
     }
     out[q] = Lat::w[0] * s + d0;
-    for (int i = 0; i < cd.n_h; ++i) out[(9 + i) * n + q] = (float)cd.C[par][i * cd.plane + off];
-    out[(9 + cd.n_h) * n + q] = cd.T[par][off];
+    bool ok = isfinite(s) && isfinite(d0);
+    for (int i = 0; i < cd.n_h; ++i) {
+        const double c = cd.C[par][i * cd.plane + off];
+        ok = ok && isfinite(c);
+        out[(9 + i) * n + q] = (float)c;
+    }
+    const float tau = cd.T[par][off];
+    out[(9 + cd.n_h) * n + q] = tau;
+    mark_nonfinite(cd, !(ok && isfinite(tau)));
+}
+
+// Scans the state of one case (level, deviations or pair moments, C_i, tau,
+// stored hbar) for non-finite values and marks the case's flag.
+__global__ __launch_bounds__(kBlock) void check_kernel(const CaseDev* __restrict__ cdp, int par) {
+    const CaseDev& cd = *cdp;
+    const int nx = cd.nx, ny = cd.ny;
+    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= (long long)nx * ny) return;
+    const int y = (int)(q / nx), x = (int)(q - (long long)y * nx);
+    const long long off = (long long)y * cd.pitch + x;
+    bool ok = isfinite(cd.P[par][off]) && isfinite(cd.T[par][off]);
+    if (cd.Q[par]) {
+        ok = ok && isfinite(cd.S[par][off]) && isfinite(cd.S[par][cd.plane + off]);
+        for (int k = 0; k < kQPlanes; ++k) ok = ok && isfinite((float)cd.Q[par][k * cd.plane + off]);
+    } else {
+        for (int a = 0; a < 8; ++a) ok = ok && isfinite(cd.S[par][a * cd.plane + off]);
+    }
+    for (int i = 0; i < cd.n_h; ++i) ok = ok && isfinite(cd.C[par][i * cd.plane + off]);
+    if (cd.H[par])
+        for (int k = 0; k < 9 * cd.n_h; ++k) ok = ok && isfinite(cd.H[par][k * cd.plane + off]);
+    mark_nonfinite(cd, !ok);
+}
+
+// Clears n flags (a fill kernel rather than a memset node, so that the call
+// may sit inside a captured graph).
+__global__ void clear_flags_kernel(unsigned int* __restrict__ flags, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flags[i] = 0u;
 }
 
 // Neumaier-compensated float64 accumulation.
@@ -221,6 +270,7 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(const CaseDev* __restric
         const long long off = (long long)y * cd.pitch + x;
         const double c1 = cd.C[par][off], c2 = cd.n_h == 2 ? cd.C[par][cd.plane + off] : 0.0;
         const double cg = comp == 0 ? c1 : (comp == 1 ? c2 : 1.0 - c1 - c2);
+        mark_nonfinite(cd, !(isfinite(ux) && isfinite(uy) && isfinite(pp) && isfinite(c1) && isfinite(c2)));
         acc[0].add(cg);
         if (cg > 0.5) acc[1].add(cg);
         acc[2].add(cg * x);
@@ -269,6 +319,16 @@ hipError_t launch_macro(const CaseDev* cd_dev, const CaseDev& cd, int par, float
 
 hipError_t launch_export(const CaseDev* cd_dev, const CaseDev& cd, int par, float* out, hipStream_t stream) {
     hipLaunchKernelGGL(export_kernel, dim3(grid_for(cd)), dim3(kBlock), 0, stream, cd_dev, par, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_check(const CaseDev* cd_dev, const CaseDev& cd, int par, hipStream_t stream) {
+    hipLaunchKernelGGL(check_kernel, dim3(grid_for(cd)), dim3(kBlock), 0, stream, cd_dev, par);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_flags(unsigned int* flags, int n, hipStream_t stream) {
+    hipLaunchKernelGGL(clear_flags_kernel, dim3((n + 63) / 64), dim3(64), 0, stream, flags, n);
     return hipGetLastError();
 }
 

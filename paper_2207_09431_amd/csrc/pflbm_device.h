@@ -68,6 +68,10 @@ struct CaseDev {
     // density ratio 1000.  The reference is exact bookkeeping: every use adds
     // it back or takes its exact differences.
     float pref_g, pref_yc;
+    // set to 1 by any once-per-call kernel that meets a non-finite value in
+    // this case's state or in the fields derived from it; cleared by the host
+    // (init_fields, set_state)
+    unsigned int* flag;
 };
 
 __device__ __forceinline__ float pref(const CaseDev& cd, int y) { return cd.pref_g * (cd.pref_yc - (float)y); }
@@ -169,6 +173,26 @@ __device__ __forceinline__ float mix_rho(const CaseDev& cd, double c1, double c2
     const double a = fmin(fmax(c1, 0.0), 1.0), b = fmin(fmax(c2, 0.0), 1.0);
     const double c = fmin(fmax(1.0 - c1 - c2, 0.0), 1.0);
     return (float)(cd.drho[0] * a + cd.drho[1] * b + cd.drho[2] * c);
+}
+
+// Isotropic central stencils from the nine values of a D2Q9 neighbourhood in
+// lattice order (f[0] the node, f[a] at x + e_a):
+//   grad f = sum_a w_a e_a [f(x+e_a) - f(x-e_a)] / (2 c_s^2),
+//   lap f  = sum_a w_a [f(x+e_a) - 2 f(x) + f(x-e_a)] / c_s^2,
+// each direction pair contributing once with twice its weight.  The step
+// kernel evaluates the same expressions on its LDS tiles, so that the fields
+// exported or reduced once per call round exactly as the step's own.
+__device__ __forceinline__ void cd_grad9(const float f[9], float& gx, float& gy) {
+    const float d1 = f[1] - f[3], d2 = f[2] - f[4], d5 = f[5] - f[7], d6 = f[6] - f[8];
+    gx = (1.0f / 3.0f) * d1 + (1.0f / 12.0f) * (d5 - d6);
+    gy = (1.0f / 3.0f) * d2 + (1.0f / 12.0f) * (d5 + d6);
+}
+// The Laplacian of the float64 phase field, rounded once.
+__device__ __forceinline__ float cd_lap9_d(const double f[9]) {
+    const double c = f[0];
+    const double s1 = (f[1] - c) + (f[3] - c), s2 = (f[2] - c) + (f[4] - c);
+    const double s5 = (f[5] - c) + (f[7] - c), s6 = (f[6] - c) + (f[8] - c);
+    return (float)((2.0 / 3.0) * (s1 + s2) + (1.0 / 6.0) * (s5 + s6));
 }
 
 // Hardware reciprocal (1 ulp), instead of the correctly rounded division

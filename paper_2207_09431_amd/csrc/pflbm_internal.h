@@ -24,6 +24,10 @@ hipError_t launch_init(const CaseDev* cd_dev, const CaseDev& cd, int par, const 
 hipError_t launch_macro(const CaseDev* cd_dev, const CaseDev& cd, int par, float* rho, float* u, float* p,
                         float* phi, hipStream_t stream);
 hipError_t launch_export(const CaseDev* cd_dev, const CaseDev& cd, int par, float* out, hipStream_t stream);
+// scan of one case's state for non-finite values (marks cd.flag)
+hipError_t launch_check(const CaseDev* cd_dev, const CaseDev& cd, int par, hipStream_t stream);
+// zeroes n non-finite flags
+hipError_t launch_clear_flags(unsigned int* flags, int n, hipStream_t stream);
 // partial sums of 6 float64 quantities into `partials` (nblocks x 6), then a
 // fixed-order final pass into `result` (6 doubles); nblocks = reduce_blocks(cd)
 int reduce_blocks(const CaseDev& cd);

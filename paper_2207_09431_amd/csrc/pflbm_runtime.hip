@@ -29,7 +29,7 @@ struct CaseLayout {
 };
 
 struct Layout {
-    size_t cases_off, tiles_off, result_off, partial_off, staging_off;
+    size_t cases_off, tiles_off, result_off, partial_off, flags_off, staging_off;
     size_t staging_bytes;
     size_t max_tiles;
     std::vector<CaseLayout> cl;
@@ -112,6 +112,8 @@ bool make_layout(const pflbm_params* cases, int n, Layout* L) {
     off = align_up(off + 8 * sizeof(double), kAlign);
     L->partial_off = off;
     off = align_up(off + 6 * sizeof(double) * kReduceMax, kAlign);
+    L->flags_off = off;                                  // one non-finite flag per case
+    off = align_up(off + sizeof(unsigned int) * n, kAlign);
     size_t maxcells = 0;
     for (int c = 0; c < n; ++c) {
         size_t cells = (size_t)cases[c].nx * cases[c].ny;
@@ -151,6 +153,7 @@ struct pflbm_ctx {
     std::vector<pflbm_params> prm;
     std::vector<CaseDev> cd;          // host copies of the device case blocks
     std::vector<int> initialised;
+    std::vector<int> nonfinite;       // sticky: a synchronising call saw the case's flag set
     Layout L;
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -193,6 +196,26 @@ const CaseDev* dev_case(const pflbm_ctx* c, int k) {
     return reinterpret_cast<const CaseDev*>(c->ws + c->L.cases_off) + k;
 }
 
+unsigned int* dev_flags(const pflbm_ctx* c) { return reinterpret_cast<unsigned int*>(c->ws + c->L.flags_off); }
+
+// Clears the non-finite flag of case k, or of every case for k < 0.
+hipError_t clear_flags(pflbm_ctx* c, int k) {
+    const int n = (int)c->prm.size();
+    if (k < 0) {
+        for (auto& v : c->nonfinite) v = 0;
+        return launch_clear_flags(dev_flags(c), n, c->stream);
+    }
+    c->nonfinite[k] = 0;
+    return launch_clear_flags(dev_flags(c) + k, 1, c->stream);
+}
+
+// True when a synchronising call has seen any case's non-finite flag set.
+bool any_nonfinite(const pflbm_ctx* c) {
+    for (int v : c->nonfinite)
+        if (v) return true;
+    return false;
+}
+
 bool all_init(const pflbm_ctx* c) {
     for (int v : c->initialised)
         if (!v) return false;
@@ -225,6 +248,7 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
     c->ws_bytes = bytes;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->initialised.assign(ncases, 0);
+    c->nonfinite.assign(ncases, 0);
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return PFLBM_ERR_DEVICE; }
     c->cd.resize(ncases);
     for (int k = 0; k < ncases; ++k) {
@@ -261,9 +285,11 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
         d.pref_yc = (float)(0.5 * (p.ny - 1));
         d.dsig12 = p.sigma12; d.dsig13 = p.sigma13; d.dsig23 = p.sigma23; d.dlam = p.Lambda;
         for (int j = 0; j < 3; ++j) { d.dSig[j] = S[j]; d.dA[j] = 4.0 * ST / (p.xi * S[j]); }
+        d.flag = reinterpret_cast<unsigned int*>(c->ws + L.flags_off) + k;
     }
     hipError_t e = hipMemcpyAsync(c->ws + L.cases_off, c->cd.data(), sizeof(CaseDev) * ncases, hipMemcpyHostToDevice,
                                   c->stream);
+    if (e == hipSuccess) e = clear_flags(c, -1);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) { delete c; return PFLBM_ERR_DEVICE; }
     int32_t st = build_tiles(c, 0);
@@ -287,6 +313,7 @@ int32_t pflbm_init_fields(pflbm_ctx* c, int32_t k, const double* C, const double
     if (e == hipSuccess && u) e = hipMemcpyAsync(du, u, sizeof(double) * 2 * n, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess && p) e = hipMemcpyAsync(dp, p, sizeof(double) * n, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_init(dev_case(c, k), c->cd[k], c->par, dC, u ? du : nullptr, p ? dp : nullptr, c->stream);
+    if (e == hipSuccess) e = clear_flags(c, k);
     // the staging area is reused by the next call: keep the host in step
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return PFLBM_ERR_DEVICE;
@@ -397,7 +424,9 @@ int32_t pflbm_autotune(pflbm_ctx* c, int32_t steps, int32_t* best, float* ms_per
     (void)hipEventDestroy(e1);
     if (st != PFLBM_OK) return st;
     if (best) *best = bestv;
-    return build_tiles(c, bestv);
+    st = build_tiles(c, bestv);
+    if (st == PFLBM_OK && any_nonfinite(c)) st = PFLBM_ERR_NONFINITE;
+    return st;
 }
 
 int32_t pflbm_macroscopic(pflbm_ctx* c, int32_t k, float* rho, float* u, float* p, float* phi) {
@@ -407,17 +436,22 @@ int32_t pflbm_macroscopic(pflbm_ctx* c, int32_t k, float* rho, float* u, float* 
     return dev_err(launch_macro(dev_case(c, k), c->cd[k], c->par, rho, u, p, phi, c->stream));
 }
 
-int32_t pflbm_bubble_centroid_velocity(pflbm_ctx* c, int32_t k, int32_t comp, double out[6]) {
-    if (!c || k < 0 || k >= (int)c->prm.size() || comp < 0 || comp > 2 || !out) return PFLBM_ERR_INVALID_ARG;
-    if (!c->initialised[k]) return PFLBM_ERR_STATE;
-    double* res = reinterpret_cast<double*>(c->ws + c->L.result_off);
-    double* part = reinterpret_cast<double*>(c->ws + c->L.partial_off);
+// The six sums of the bubble diagnostics of case k into out (shared by the
+// workspace and the no-allocation entry points; `part` holds
+// reduce_blocks() x 6 partials, `res` 6 results).
+static int32_t centroid_sums(pflbm_ctx* c, int32_t k, int32_t comp, double* part, double* res, double out[6]) {
     hipError_t e = launch_reduce(dev_case(c, k), c->cd[k], c->par, comp, part, res, c->stream);
     double sums[6];
+    unsigned int flag = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(sums, res, sizeof(sums), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, dev_flags(c) + k, sizeof(flag), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return PFLBM_ERR_DEVICE;
+    if (flag) c->nonfinite[k] = 1;
+    if (c->nonfinite[k]) return PFLBM_ERR_NONFINITE;
     for (int j = 0; j < 6; ++j) if (!is_finite(sums[j])) return PFLBM_ERR_NONFINITE;
+    // a component with no mass has no centroid or mean velocity
+    if (sums[0] == 0.0) return PFLBM_ERR_NONFINITE;
     const double m = sums[0];
     out[0] = m;
     out[1] = sums[1];
@@ -426,6 +460,36 @@ int32_t pflbm_bubble_centroid_velocity(pflbm_ctx* c, int32_t k, int32_t comp, do
     out[4] = sums[4] / m;
     out[5] = sums[5] / m;
     return PFLBM_OK;
+}
+
+int32_t pflbm_bubble_centroid_velocity(pflbm_ctx* c, int32_t k, int32_t comp, double out[6]) {
+    if (!c || k < 0 || k >= (int)c->prm.size() || comp < 0 || comp > 2 || !out) return PFLBM_ERR_INVALID_ARG;
+    if (comp == 1 && c->prm[k].n_h == 1) return PFLBM_ERR_INVALID_ARG;   // C_2 is not carried
+    if (!c->initialised[k]) return PFLBM_ERR_STATE;
+    double* res = reinterpret_cast<double*>(c->ws + c->L.result_off);
+    double* part = reinterpret_cast<double*>(c->ws + c->L.partial_off);
+    return centroid_sums(c, k, comp, part, res, out);
+}
+
+int32_t pflbm_check_state(pflbm_ctx* c) {
+    if (!c) return PFLBM_ERR_INVALID_ARG;
+    if (!all_init(c)) return PFLBM_ERR_STATE;
+    const int n = (int)c->prm.size();
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n && e == hipSuccess; ++k) e = launch_check(dev_case(c, k), c->cd[k], c->par, c->stream);
+    std::vector<unsigned int> flags(n, 0u);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(flags.data(), dev_flags(c), sizeof(unsigned int) * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return PFLBM_ERR_DEVICE;
+    for (int k = 0; k < n; ++k)
+        if (flags[k]) c->nonfinite[k] = 1;
+    return any_nonfinite(c) ? PFLBM_ERR_NONFINITE : PFLBM_OK;
+}
+
+int32_t pflbm_case_nonfinite(const pflbm_ctx* c, int32_t k) {
+    if (!c || k < 0 || k >= (int)c->prm.size()) return PFLBM_ERR_INVALID_ARG;
+    return c->nonfinite[k] ? 1 : 0;
 }
 
 size_t pflbm_state_bytes(const pflbm_ctx* c) {
@@ -459,6 +523,7 @@ int32_t pflbm_set_state(pflbm_ctx* c, const void* d_src, size_t bytes) {
     if (!c || !d_src) return PFLBM_ERR_INVALID_ARG;
     if (bytes < pflbm_state_bytes(c)) return PFLBM_ERR_WORKSPACE;
     int32_t st = copy_state(c, nullptr, static_cast<const char*>(d_src), true);
+    if (st == PFLBM_OK && clear_flags(c, -1) != hipSuccess) st = PFLBM_ERR_DEVICE;
     if (st == PFLBM_OK) for (auto& v : c->initialised) v = 1;
     return st;
 }

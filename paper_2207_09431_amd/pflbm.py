@@ -23,7 +23,7 @@ EXPORTS = ("pflbm_workspace_bytes", "pflbm_create", "pflbm_init_fields", "pflbm_
            "pflbm_bubble_centroid_velocity", "pflbm_state_bytes", "pflbm_get_state", "pflbm_set_state",
            "pflbm_export_populations", "pflbm_num_variants", "pflbm_variant_name", "pflbm_set_variant",
            "pflbm_autotune", "pflbm_set_graph", "pflbm_stream", "pflbm_bytes_per_update", "pflbm_destroy",
-           "pflbm_status_string")
+           "pflbm_status_string", "pflbm_check_state", "pflbm_case_nonfinite")
 
 
 class PflbmError(RuntimeError):
@@ -107,6 +107,10 @@ def lib():
         L.pflbm_destroy.restype = i32
         L.pflbm_status_string.argtypes = [i32]
         L.pflbm_status_string.restype = ct.c_char_p
+        L.pflbm_check_state.argtypes = [vp]
+        L.pflbm_check_state.restype = i32
+        L.pflbm_case_nonfinite.argtypes = [vp, i32]
+        L.pflbm_case_nonfinite.restype = i32
         _lib = L
     return _lib
 
@@ -167,8 +171,25 @@ class Solver:
             pass
 
     def init_fields(self, case_id, C, u=None, p=None):
+        prm = self._case_params(case_id, "pflbm_init_fields")
+        ny, nx, nh = prm["ny"], prm["nx"], prm["n_h"]
         C, u, p = _f64(C), _f64(u), _f64(p)
+        # the ABI reads exactly n_h, 2 and 1 planes of (ny, nx): reject other shapes here
+        for name, a, shape in (("C", C, (nh, ny, nx)), ("u", u, (2, ny, nx)), ("p", p, (ny, nx))):
+            if a is not None and a.shape != shape and not (name == "C" and nh == 1 and a.shape == (ny, nx)):
+                raise PflbmError(f"pflbm_init_fields: {name} has shape {a.shape}, expected {shape}", -1)
         _check("pflbm_init_fields", lib().pflbm_init_fields(self._h, int(case_id), _dp(C), _dp(u), _dp(p)))
+
+    def check_state(self):
+        """Scans every case's state; raises PflbmError(-4) if any is non-finite."""
+        _check("pflbm_check_state", lib().pflbm_check_state(self._h))
+
+    def case_nonfinite(self, case_id=0):
+        """True if the case was flagged non-finite by a synchronising call."""
+        r = lib().pflbm_case_nonfinite(self._h, int(case_id))
+        if r < 0:
+            raise PflbmError("pflbm_case_nonfinite", r)
+        return bool(r)
 
     def step(self, n=1):
         _check("pflbm_step", lib().pflbm_step(self._h, int(n)))

@@ -2,7 +2,7 @@
 together in one batched solver on the GPU, with the drag post-processing of
 Sec. 4.1.
 
-    python -m paper_2207_09431_amd.sweep [--ratio 200] [--cases 3,4,5,6] [--steps 60000]
+    python -m paper_2207_09431_amd.sweep [--ratio 200] [--cases 3,4,5,6] [--steps 60000] [--scale 2]
 
 prints one JSON object per case.  The terminal velocity is read as the
 largest sampled mean rise velocity (Eq. (44)) before the bubble comes within
@@ -41,7 +41,9 @@ def run_sweep(cases: list, max_steps: int, every: int = 1000, solver_factory=Sol
                 continue
             try:
                 diag = s.bubble_centroid_velocity(i, 0)
-            except PflbmError:
+            except PflbmError as e:
+                if e.status != -4:         # only a diverged state ends a case quietly
+                    raise
                 alive[i] = False
                 end[i] = f"nonfinite by step {done}"
                 continue
@@ -87,14 +89,21 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--ratio", type=float, default=200.0, help="liquid/gas density ratio (the paper's is 800)")
     ap.add_argument("--cases", default="1,2,3,4,5,6", help="Table 5 cases to run (1-based)")
-    ap.add_argument("--steps", type=int, default=60000)
-    ap.add_argument("--every", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="steps on the 200 x 400 lattice (default 60,000); multiplied by scale^2")
+    ap.add_argument("--every", type=int, default=None,
+                    help="sampling interval on the 200 x 400 lattice (default 1,000); multiplied by scale^2")
     ap.add_argument("--scale", type=int, default=1,
                     help="lattice f times finer than 200 x 400 at the same Re, Eo and Mo")
     a = ap.parse_args(argv)
+    # at fixed Re, Eo and Mo lattice velocities scale by 1/f and lengths by f,
+    # so the same physical time takes f^2 times the steps
+    f2 = a.scale * a.scale
+    steps = (60000 if a.steps is None else a.steps) * f2
+    every = (1000 if a.every is None else a.every) * f2
     all_cases = inputs.shear_thinning_sweep(density_ratio=a.ratio, scale=a.scale)
     pick = [int(x) - 1 for x in a.cases.split(",")]
-    for r in run_sweep([all_cases[i] for i in pick], a.steps, a.every):
+    for r in run_sweep([all_cases[i] for i in pick], steps, every):
         r = dict(r)
         r.pop("samples")
         print(json.dumps(r), flush=True)

@@ -9,7 +9,7 @@ import pytest
 
 from oracle.pfo import run_case
 from paper_2207_09431_amd import inputs
-from helpers import rel_l2
+from helpers import max_norms, rel_l2
 
 pytestmark = pytest.mark.gpu
 TOL16 = 1e-3
@@ -38,8 +38,12 @@ def gpu_run(case, steps, variant=None, **over):
 
 
 def errors(m, o):
+    """Relative L2 of u and C (returned; callers bound them), with the
+    pointwise errors held to 10 x the float16 bound here."""
     ru, rc = rel_l2(m["u"], o["u"]), rel_l2(m["phi"], o["phi"])
-    print(f"rel-L2 u {ru:.3e}  C {rc:.3e}  p {rel_l2(m['p'], o['p']):.3e}", flush=True)
+    mu, mc = max_norms(m, o)
+    print(f"rel-L2 u {ru:.3e}  C {rc:.3e}  p {rel_l2(m['p'], o['p']):.3e}  max u {mu:.2e} C {mc:.2e}", flush=True)
+    assert mu <= 10 * TOL16 and mc <= 10 * TOL16, (mu, mc)
     return ru, rc
 
 

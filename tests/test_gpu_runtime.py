@@ -93,3 +93,101 @@ def test_checkpoints_of_two_runs_are_bitwise_equal(Solver):
         states.append(s.get_state().cpu().numpy())
         s.close()
     assert np.array_equal(states[0], states[1])
+
+
+def _status(call):
+    from paper_2207_09431_amd.pflbm import PflbmError
+    try:
+        call()
+    except PflbmError as e:
+        return e.status
+    return 0
+
+
+def test_nonfinite_flag_is_sticky(Solver):
+    """A NaN planted in a copy of the state (level s of one node) through
+    set_state: the next synchronising calls return NONFINITE (-4) and keep
+    doing so; stepping stays possible (asynchronous); set_state with a finite
+    state or init_fields clears the flag.  A NaN only in tau is found by the
+    state scan."""
+    import torch
+    case = inputs.rising_bubble_small()
+    s = Solver(case["params"])
+    s.init_fields(0, case["C"], case["u"], case["p"])
+    s.step(3)
+    good = s.get_state()
+    assert _status(s.check_state) == 0
+    bad = good.clone()
+    bad.view(torch.float64)[200] = float("nan")      # the level plane comes first
+    s.set_state(bad)
+    assert not s.case_nonfinite(0)
+    assert _status(lambda: s.bubble_centroid_velocity(0, 0)) == -4
+    assert s.case_nonfinite(0)
+    assert _status(s.check_state) == -4
+    assert _status(lambda: s.bubble_centroid_velocity(0, 2)) == -4
+    s.step(2)
+    assert _status(s.check_state) == -4
+    s.set_state(good)
+    assert _status(s.check_state) == 0 and not s.case_nonfinite(0)
+    assert _status(lambda: s.bubble_centroid_velocity(0, 0)) == 0
+    # macroscopic (asynchronous) marks the device flag; the next synchronising call reports it
+    s.set_state(bad)
+    s.macroscopic(0)
+    s.synchronize()
+    assert not s.case_nonfinite(0)
+    assert _status(lambda: s.bubble_centroid_velocity(0, 0)) == -4
+    s.init_fields(0, case["C"], case["u"], case["p"])
+    assert _status(s.check_state) == 0
+    # a NaN confined to tau (the last plane of the state)
+    taubad = good.clone()
+    tv = taubad.view(torch.float32)
+    tv[tv.numel() - 1000] = float("nan")
+    s.set_state(taubad)
+    assert _status(s.check_state) == -4
+
+
+def test_nonfinite_flag_is_per_case(Solver):
+    """In a batch, a non-finite case does not flag the others, which can be
+    advanced and reduced; init_fields of the bad case clears it."""
+    import torch
+    cases = [inputs.rising_bubble_small(), inputs.static_bubble(nx=70, ny=45, radius=12.0)]
+    b = Solver([c["params"] for c in cases])
+    for k, c in enumerate(cases):
+        b.init_fields(k, c["C"], c["u"], c["p"])
+    good = b.get_state()
+    bad = good.clone()
+    bad.view(torch.float64)[100] = float("inf")      # case 0 comes first in the state
+    b.set_state(bad)
+    assert _status(b.check_state) == -4
+    assert b.case_nonfinite(0) and not b.case_nonfinite(1)
+    b.step(4)
+    assert _status(lambda: b.bubble_centroid_velocity(1, 0)) == 0
+    assert _status(lambda: b.bubble_centroid_velocity(0, 0)) == -4
+    b.init_fields(0, cases[0]["C"], cases[0]["u"], cases[0]["p"])
+    assert _status(b.check_state) == 0
+
+
+def test_centroid_arguments(Solver):
+    """Component 1 (C_2) is not carried with one phase field (INVALID_ARG);
+    a component with zero mass has no centroid (NONFINITE, not sticky)."""
+    import numpy as np
+    case = inputs.rising_bubble_small()
+    s = Solver(case["params"])
+    s.init_fields(0, case["C"], case["u"], case["p"])
+    assert _status(lambda: s.bubble_centroid_velocity(0, 1)) == -1
+    s.init_fields(0, np.zeros_like(case["C"]))
+    assert _status(lambda: s.bubble_centroid_velocity(0, 0)) == -4
+    assert not s.case_nonfinite(0)
+    assert _status(s.check_state) == 0
+    assert s.bubble_centroid_velocity(0, 2)[0] == 64 * 128
+
+
+def test_init_fields_rejects_wrong_shapes(Solver):
+    """The binding checks the shapes of the host fields against the case
+    before the ABI reads nx * ny values per plane."""
+    case = inputs.three_component(nx=96, ny=192)
+    s = Solver(case["params"])
+    for C, u, p in ((case["C"][:1], None, None), (case["C"].transpose(0, 2, 1).copy(), None, None),
+                    (case["C"], np.zeros((2, 191, 96)), None), (case["C"], None, np.zeros((96, 192)))):
+        assert _status(lambda: s.init_fields(0, C, u, p)) == -1
+    s.init_fields(0, case["C"])

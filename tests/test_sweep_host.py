@@ -53,7 +53,7 @@ class Scripted:
     def bubble_centroid_velocity(self, i, comp):
         v = self.scripts[i](self.t)
         if v is None:
-            raise PflbmError(-4, "pflbm_bubble_centroid_velocity")
+            raise PflbmError("pflbm_bubble_centroid_velocity", -4)
         return np.array([math.pi * R * R, 0.0, 30.0, self.yc(i), 0.0, v])
 
     def macroscopic(self, i):
