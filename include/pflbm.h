@@ -159,6 +159,24 @@ int32_t pflbm_macroscopic(pflbm_ctx* ctx, int32_t case_id, float* d_rho, float* 
 int32_t pflbm_bubble_centroid_velocity(pflbm_ctx* ctx, int32_t case_id, int32_t comp, double out[6]);
 
 /*
+ * The same diagnostics for callers that cannot allocate device memory or
+ * touch their own workspace's scratch region at this point (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation).
+ * Identical arguments, results (bitwise: the same kernels in the same order)
+ * and errors as pflbm_bubble_centroid_velocity; the reduction's partial sums
+ * and results are kept in a static device array of the library
+ * (1024 x 6 + 8 doubles = 49,216 bytes per GPU, held until the process
+ * ends) instead of the workspace.  Calls no allocating routine.  Every call
+ * on one GPU shares that array: calls that overlap on one GPU (different
+ * streams or host threads) race and must be serialised by the caller; each
+ * call overwrites every slot it reads, so no clearing is needed between
+ * calls.  Errors additionally: WORKSPACE if a reduction would need more than
+ * the array's 1024 partial rows (the reduction caps its grid there, so no
+ * domain size does).  Synchronises the stream.
+ */
+int32_t pflbm_bubble_centroid_velocity_noalloc(pflbm_ctx* ctx, int32_t case_id, int32_t comp, double out[6]);
+
+/*
  * Divergence detection (sticky NONFINITE).  Every case carries a device flag
  * that the once-per-call kernels (pflbm_macroscopic,
  * pflbm_bubble_centroid_velocity, pflbm_export_populations and the scan

@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "pflbm.h"
@@ -21,6 +22,33 @@ constexpr int kPitchElems = 64;
 constexpr int kReduceMax = 1024;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Scratch of pflbm_bubble_centroid_velocity_noalloc: the reduction partials
+// of at most kReduceMax blocks (6 float64 each) followed by the 6 final sums
+// (8 slots).  One copy per GPU, held until the process ends; host code uses
+// the address resolved per device below, never the symbol itself.
+constexpr size_t kScratchDoubles = 6 * (size_t)kReduceMax + 8;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, resolved once per device with
+// that device current (the caller's current device at pflbm_create).
+hipError_t scratch_address(int device, double** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 struct CaseLayout {
     size_t P[2], S[2], C[2], T[2], H[2], Q[2];   // byte offsets into the workspace; P[b] starts buffer b
@@ -162,6 +190,7 @@ struct pflbm_ctx {
     int variant = 0;
     int ntiles = 0;
     int device = 0;
+    double* scratch = nullptr;           // this device's copy of `scratch`
     // replay of a captured pair of steps (parity 0 -> 1 -> 0)
     int graph_steps = 0;                 // 0: plain launches
     hipGraphExec_t graph = nullptr;
@@ -250,6 +279,7 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
     c->initialised.assign(ncases, 0);
     c->nonfinite.assign(ncases, 0);
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return PFLBM_ERR_DEVICE; }
+    if (scratch_address(c->device, &c->scratch) != hipSuccess) { delete c; return PFLBM_ERR_DEVICE; }
     c->cd.resize(ncases);
     for (int k = 0; k < ncases; ++k) {
         const pflbm_params& p = cases[k];
@@ -468,6 +498,20 @@ int32_t pflbm_bubble_centroid_velocity(pflbm_ctx* c, int32_t k, int32_t comp, do
     if (!c->initialised[k]) return PFLBM_ERR_STATE;
     double* res = reinterpret_cast<double*>(c->ws + c->L.result_off);
     double* part = reinterpret_cast<double*>(c->ws + c->L.partial_off);
+    return centroid_sums(c, k, comp, part, res, out);
+}
+
+int32_t pflbm_bubble_centroid_velocity_noalloc(pflbm_ctx* c, int32_t k, int32_t comp, double out[6]) {
+    if (!c || k < 0 || k >= (int)c->prm.size() || comp < 0 || comp > 2 || !out) return PFLBM_ERR_INVALID_ARG;
+    if (comp == 1 && c->prm[k].n_h == 1) return PFLBM_ERR_INVALID_ARG;
+    if (!c->initialised[k]) return PFLBM_ERR_STATE;
+    // the partials of every reduction block and the 6 sums must fit the
+    // static scratch (the reduction caps its grid at kReduceMax blocks, so
+    // every domain size fits; the check guards the layout)
+    const int nb = reduce_blocks(c->cd[k]);
+    if (nb <= 0 || (size_t)nb * 6 + 8 > kScratchDoubles) return PFLBM_ERR_WORKSPACE;
+    double* part = c->scratch;
+    double* res = c->scratch + 6 * (size_t)kReduceMax;
     return centroid_sums(c, k, comp, part, res, out);
 }
 

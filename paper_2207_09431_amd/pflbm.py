@@ -23,7 +23,8 @@ EXPORTS = ("pflbm_workspace_bytes", "pflbm_create", "pflbm_init_fields", "pflbm_
            "pflbm_bubble_centroid_velocity", "pflbm_state_bytes", "pflbm_get_state", "pflbm_set_state",
            "pflbm_export_populations", "pflbm_num_variants", "pflbm_variant_name", "pflbm_set_variant",
            "pflbm_autotune", "pflbm_set_graph", "pflbm_stream", "pflbm_bytes_per_update", "pflbm_destroy",
-           "pflbm_status_string", "pflbm_check_state", "pflbm_case_nonfinite")
+           "pflbm_status_string", "pflbm_check_state", "pflbm_case_nonfinite",
+           "pflbm_bubble_centroid_velocity_noalloc")
 
 
 class PflbmError(RuntimeError):
@@ -107,6 +108,8 @@ def lib():
         L.pflbm_destroy.restype = i32
         L.pflbm_status_string.argtypes = [i32]
         L.pflbm_status_string.restype = ct.c_char_p
+        L.pflbm_bubble_centroid_velocity_noalloc.argtypes = [vp, i32, i32, dp]
+        L.pflbm_bubble_centroid_velocity_noalloc.restype = i32
         L.pflbm_check_state.argtypes = [vp]
         L.pflbm_check_state.restype = i32
         L.pflbm_case_nonfinite.argtypes = [vp, i32]
@@ -217,6 +220,14 @@ class Solver:
         out = np.empty(6)
         _check("pflbm_bubble_centroid_velocity",
                lib().pflbm_bubble_centroid_velocity(self._h, int(case_id), int(comp), _dp(out)))
+        return out
+
+    def bubble_centroid_velocity_noalloc(self, case_id=0, comp=0):
+        """bubble_centroid_velocity with the reduction's scratch in the
+        library's static device array (no workspace, no allocation)."""
+        out = np.empty(6)
+        _check("pflbm_bubble_centroid_velocity_noalloc",
+               lib().pflbm_bubble_centroid_velocity_noalloc(self._h, int(case_id), int(comp), _dp(out)))
         return out
 
     def state_bytes(self):
