@@ -72,6 +72,12 @@ typedef struct {
                                   (the paper's explicit update, Sec. 2.3); m in 1..8: m fixed-point
                                   passes tau <- tau(gdot(tau)) of the implicit relation Eq. (32),
                                   started from the previous step's tau */
+    int32_t hforce_cd;         /* stencil of (e_a - u).grad C_i in the hbar forcing (Eq. (18)):
+                                  0 mixed directional differences (default), 1 central differences.
+                                  The paper names both kinds (Sec. 2.2, after Eq. (21)) without
+                                  assigning them to terms.  With variable mobility (Eq. (6)) use 1:
+                                  in a phase where D_i vanishes the mixed form amplifies oblique
+                                  modes (up to 1.148 per step), the central form does not */
 } pflbm_params;
 
 /*
@@ -107,8 +113,8 @@ size_t pflbm_workspace_bytes(const pflbm_params* cases, int32_t ncases);
  * (nx or ny < 5, n_h not 1 or 2, rho_k <= 0, nu_k <= 0, nu_min <= 0 or
  * nu_min > nu_max, K <= 0 with a power-law component, xi <= 0, D0 < 0,
  * tau_h <= 0, a Sigma_i <= 0, store_h = 0 with tau_h != 0.5, storage not
- * 0 or 1, tau_iterations outside 0..8, nx rounded up to 64 times ny at or
- * above 2^29 nodes);
+ * 0 or 1, tau_iterations outside 0..8, hforce_cd not 0 or 1, nx rounded up
+ * to 64 times ny at or above 2^29 nodes);
  * UNSUPPORTED for storage = 1 with store_h = 1; WORKSPACE when the
  * workspace is NULL, small or misaligned; DEVICE when a HIP call fails.
  */

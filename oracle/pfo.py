@@ -45,6 +45,10 @@ class Params(ct.Structure):
 
 
 def make_params(d: dict) -> Params:
+    """Parameter block from a case's dict.  The case dicts carry the HIP
+    library's name `hforce_cd` (1: central differences for grad C_i in the
+    hbar forcing), which is this oracle's hforce_mode = 1 unless hforce_mode
+    is given."""
     p = Params()
     for name, typ in Params._fields_:
         if name in ("rho", "nu"):
@@ -52,6 +56,8 @@ def make_params(d: dict) -> Params:
             setattr(p, name, arr)
         elif name in d:
             setattr(p, name, d[name])
+    if d.get("hforce_cd") and "hforce_mode" not in d:
+        p.hforce_mode = 1
     return p
 
 

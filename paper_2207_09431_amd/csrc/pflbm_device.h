@@ -51,6 +51,7 @@ struct CaseDev {
     int plc;            // power-law component or -1
     int vm;             // variable mobility
     int tau_iters;      // fixed-point passes of the implicit tau (0: previous step's tau)
+    int hcd;            // central differences for grad C_i in the hbar forcing
     float K, nexp, numin, numax;
     float sig12, sig13, sig23, lam;
     float Sig[3];

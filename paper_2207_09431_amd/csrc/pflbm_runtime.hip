@@ -97,6 +97,7 @@ bool valid_params(const pflbm_params& p) {
     if (p.store_h != 0 && p.store_h != 1) return false;
     if (!p.store_h && p.tau_h != 0.5) return false;
     if (p.tau_iterations < 0 || p.tau_iterations > 8) return false;
+    if (p.hforce_cd != 0 && p.hforce_cd != 1) return false;
     return true;
 }
 
@@ -301,6 +302,7 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
         d.plc = p.powerlaw_comp;
         d.vm = p.variable_mobility ? 1 : 0;
         d.tau_iters = p.tau_iterations;
+        d.hcd = p.hforce_cd;
         d.K = (float)p.K; d.nexp = (float)p.n; d.numin = (float)p.nu_min; d.numax = (float)p.nu_max;
         d.sig12 = (float)p.sigma12; d.sig13 = (float)p.sigma13; d.sig23 = (float)p.sigma23; d.lam = (float)p.Lambda;
         double S[3], ST;

@@ -477,39 +477,49 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const float bx = gpx - Fx, by = gpy - Fy;
         const float ub = ux * bx + uy * by;
         const float r3 = 3.0f * rcp(rho);
+        // The forcing's (e_a-u).grad C_i takes the mixed directional
+        // derivatives (the default) or, with hforce_cd, central differences:
+        // then e_a.grad C_i joins the terms affine in e_a.  One copy of the
+        // block per choice, selected by a uniform branch.
+        auto hbar_block = [&](auto cd_tag) {
+            constexpr bool HCD = decltype(cd_tag)::value;
 #pragma unroll
-        for (int i = 0; i < NH; ++i) {
-            const float kk = c[i] * r3;                // C_i / (rho c_s^2)
-            const float Xx = gcx[i] - kk * bx, Xy = gcy[i] - kk * by;
-            const float uX = ux * Xx + uy * Xy;
-            const float umc = (i == 0) ? um1 : um2;
-            if (SH) {
-                // stored hbar_a = w_a C + q_a: hbar*_a = w_a C + (1 - omega_h) q_a + Q_a with
-                //   Q_a = omega_h w_a A_a C + Gamma_a [-omega_h (e_a-u).X / 2 + forcing + Dif / 2]
-                //       = w_a [H_a + A_a (omega_h C + H_a)];  Q_a is parked, the q_a term is
-                // added by the receiver, and w_a C streams in float64 there
-                const float oh = cd.omh;
-                const float H0 = fmaf(0.5f * oh, uX, fmaf(kk, ub, 0.5f * dif[i])) - umc;
-                const float Hx = fmaf(0.5f * oh, Xx, kk * bx), Hy = fmaf(0.5f * oh, Xy, kk * by);
-                const float oc = oh * c[i];
+            for (int i = 0; i < NH; ++i) {
+                const float kk = c[i] * r3;                // C_i / (rho c_s^2)
+                const float Xx = gcx[i] - kk * bx, Xy = gcy[i] - kk * by;
+                const float uX = ux * Xx + uy * Xy;
+                const float umc = HCD ? ux * gcx[i] + uy * gcy[i] : ((i == 0) ? um1 : um2);
+                const float fgx = HCD ? gcx[i] : 0.0f, fgy = HCD ? gcy[i] : 0.0f;
+                if (SH) {
+                    // stored hbar_a = w_a C + q_a: hbar*_a = w_a C + (1 - omega_h) q_a + Q_a with
+                    //   Q_a = omega_h w_a A_a C + Gamma_a [-omega_h (e_a-u).X / 2 + forcing + Dif / 2]
+                    //       = w_a [H_a + A_a (omega_h C + H_a)];  Q_a is parked, the q_a term is
+                    // added by the receiver, and w_a C streams in float64 there
+                    const float oh = cd.omh;
+                    const float H0 = fmaf(0.5f * oh, uX, fmaf(kk, ub, 0.5f * dif[i])) - umc;
+                    const float Hx = fmaf(0.5f * oh, Xx, kk * bx) - fgx, Hy = fmaf(0.5f * oh, Xy, kk * by) - fgy;
+                    const float oc = oh * c[i];
 #pragma unroll
-                for (int a = 0; a < 9; ++a) {
-                    const float H = (H0 + dc[i][a]) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
-                    sH[i][a][idx] = Lat::w[a] * fmaf(A[a], oc + H, H);
+                    for (int a = 0; a < 9; ++a) {
+                        const float H = (HCD ? H0 : H0 + dc[i][a]) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
+                        sH[i][a][idx] = Lat::w[a] * fmaf(A[a], oc + H, H);
+                    }
+                } else {
+                    // omega_h = 1: hbar* - w_a C = w_a A_a C + Gamma_a H_a
+                    //   = w_a [H_a + A_a (C + H_a)],  H_a = -(e_a-u).X / 2 + forcing + Dif / 2
+                    const float H0 = fmaf(0.5f, uX, fmaf(kk, ub, 0.5f * dif[i])) - umc;
+                    const float Hx = fmaf(0.5f, Xx, kk * bx) - fgx, Hy = fmaf(0.5f, Xy, kk * by) - fgy;
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) {
+                        const float H = (HCD ? H0 : H0 + dc[i][a]) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
+                        sH[i][a][idx] = Lat::w[a] * fmaf(A[a], c[i] + H, H);
+                    }
                 }
-            } else {
-                // omega_h = 1: hbar* - w_a C = w_a A_a C + Gamma_a H_a
-                //   = w_a [H_a + A_a (C + H_a)],  H_a = -(e_a-u).X / 2 + forcing + Dif / 2
-                const float H0 = fmaf(0.5f, uX, fmaf(kk, ub, 0.5f * dif[i])) - umc;
-                const float Hx = fmaf(0.5f, Xx, kk * bx), Hy = fmaf(0.5f, Xy, kk * by);
-#pragma unroll
-                for (int a = 0; a < 9; ++a) {
-                    const float H = (H0 + dc[i][a]) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
-                    sH[i][a][idx] = Lat::w[a] * fmaf(A[a], c[i] + H, H);
-                }
+                sDif[i][idx] = dif[i];
             }
-            sDif[i][idx] = dif[i];
-        }
+        };
+        if (cd.hcd) hbar_block(std::true_type{});
+        else hbar_block(std::false_type{});
         // tau is written for the tile's own nodes
         const int ox = rx - 1, oy = ry - 1;
         if (ox >= 0 && ox < TX && oy >= 0 && oy < TY && x0 + ox < nx)

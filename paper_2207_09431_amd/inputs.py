@@ -115,7 +115,7 @@ def default_params(nx: int, ny: int) -> dict:
         sigma12=1e-3, sigma13=1e-3, sigma23=1e-3, Lambda=0.0,
         xi=4.0, D0=4.0 / 300.0, variable_mobility=1,
         tau_h=0.5, g=0.0, fx=0.0,
-        storage=0, store_h=0,
+        storage=0, store_h=0, hforce_cd=0,
     )
 
 
@@ -284,6 +284,31 @@ def three_component(variable_mobility: int = 0, nx: int = 256, ny: int = 512,
     c2 = bubble_field(nx, ny, [b2], prm["xi"])
     C = np.stack([c1, c2])
     return _case(prm, C, None, None, f"three_component_{nx}x{ny}")
+
+
+def bubble_droplet(variable_mobility: int = 1, nx: int = 200, ny: int = 400, tau3: float = 0.5,
+                   r_bubble: float = 20.0, r_drop: float = 25.0, gap: float = 10.0, hforce_cd: int = 1) -> dict:
+    """The three-component system of Sec. 3.1 (Table 1): a light bubble
+    (component 2, rho_2 = 0.01) rising under g = 1e-6 towards a droplet of
+    the liquid's density (component 1, rho_1 = rho_3 = 1) in the liquid
+    (component 3), all sigma_ij = 1e-4, tau_1/tau_3 = tau_2/tau_3 = 2, on a
+    200 x 400 lattice.  The paper shows the initial state only as a figure and
+    gives no tau_3; here tau_3 = 1/2 (nu = c_s^2 tau), the droplet (radius
+    r_drop) is centred at (nx/2, ny/2) and the bubble (radius r_bubble) on the
+    same vertical line `gap` lattice units below it.  D0 = xi/300 (Sec. 2.1).
+    hforce_cd selects central differences for grad C_i in the hbar forcing,
+    the reading under which variable mobility is stable."""
+    prm = default_params(nx, ny)
+    nu3 = tau3 / 3.0
+    prm.update(n_h=2, rho=[1.0, 0.01, 1.0], nu=[2.0 * nu3, 2.0 * nu3, nu3], powerlaw_comp=-1, n=1.0,
+               sigma12=1e-4, sigma13=1e-4, sigma23=1e-4, Lambda=0.0, variable_mobility=variable_mobility,
+               D0=prm["xi"] / 300.0, g=1e-6, hforce_cd=hforce_cd)
+    yd = ny / 2.0
+    yb = yd - r_drop - gap - r_bubble
+    c1 = bubble_field(nx, ny, [(nx / 2.0, yd, r_drop)], prm["xi"])
+    c2 = bubble_field(nx, ny, [(nx / 2.0, yb, r_bubble)], prm["xi"])
+    return _case(prm, np.stack([c1, c2]), None, None,
+                 f"bubble_droplet_{nx}x{ny}_{'variable' if variable_mobility else 'constant'}_mobility")
 
 
 def place_bubbles(nx: int, ny: int, count: int, rmin: float, rmax: float, xi: float, seed: int,

@@ -45,7 +45,7 @@ class Params(ct.Structure):
         ("tau_h", ct.c_double),
         ("g", ct.c_double), ("fx", ct.c_double),
         ("storage", ct.c_int32), ("store_h", ct.c_int32),
-        ("tau_iterations", ct.c_int32),
+        ("tau_iterations", ct.c_int32), ("hforce_cd", ct.c_int32),
     ]
 
 

@@ -22,6 +22,7 @@ import numpy as np
 import pytest
 
 from oracle.pfo import Oracle
+from paper_2207_09431_amd import inputs
 
 NX, NY, XI, W0, SIGMA, D0 = 96, 5, 8.0, 16.0, 1e-3, 0.01
 R = NX / 4
@@ -85,3 +86,66 @@ def test_diffusion_source_matches_continuum_operator(variable, tol):
         # fails by a wide margin, so the pin sees that term
         ref_ng = smooth(continuum_source(True, gradient_term=False))
         assert np.abs(obs - ref_ng).max() / np.abs(ref_ng).max() > 5 * tol
+
+
+def _amplification(kx, ky, mixed):
+    """Amplification per step of a Fourier mode exp(i k.x) of C under the hbar
+    update in a uniform phase with zero mobility, no force and u = 0 (Eq. (18)
+    with tau_h = 1/2, so the post-collision hbar is hbar_eq plus the forcing):
+      C(t+1) = sum_a w_a S_a [C - (1/2) e_a.grad C + F_a C],
+    S_a = exp(-i k.e_a) the streaming shift, grad the isotropic central
+    gradient, F_a the stencil of (e_a - u).grad C in the forcing: the mixed
+    directional difference [-C(x+2e) + 5C(x+e) - 3C(x) - C(x-e)]/4 or the
+    central e_a.grad C.  Derived from the stencils' definitions, independently
+    of the oracle."""
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1]); ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+    w = np.array([4, 1, 1, 1, 1, 0.25, 0.25, 0.25, 0.25]) / 9.0
+    ke = kx * ex + ky * ey
+    sx, sy = 3 * np.sum(w * ex * np.sin(ke)), 3 * np.sum(w * ey * np.sin(ke))
+    edg = 1j * (ex * sx + ey * sy)
+    if mixed:
+        F = (-np.exp(2j * ke) + 5 * np.exp(1j * ke) - 3 - np.exp(-1j * ke)) / 4
+        F[0] = 0.0
+    else:
+        F = edg
+    return abs(np.sum(w * np.exp(-1j * ke) * (1 - 0.5 * edg + F)))
+
+
+@pytest.mark.parametrize("hforce_mode", [0, 1])
+def test_hbar_update_without_mobility_grows_at_its_amplification_factor(hforce_mode):
+    """Why variable mobility needs central differences in the hbar forcing.
+    Without mobility (D0 = 0) in a uniform phase, the mixed directional
+    derivative of (e_a - u).grad C amplifies oblique modes: the largest
+    factor is 1.1481 per step at k = (pi/2, pi) (about 4 per 10 steps), while
+    on the lattice axes and everywhere with central differences it is at most
+    1.  The oracle, started from 1e-12 noise on C = 0.3 with equal densities,
+    no surface tension and no gravity (so u stays 0 and the update is linear
+    in C), grows at the largest factor (walls and the finite box take ~1 %
+    of it) with the mixed form and decays with the central one.  Constant
+    mobility damps these modes through the bulk Cahn-Hilliard term; variable
+    mobility C(1-C) vanishes in a bulk phase and leaves them undamped."""
+    k = np.linspace(-np.pi, np.pi, 97)
+    g = np.array([[_amplification(a, b, hforce_mode == 0) for a in k] for b in k])
+    if hforce_mode == 0:
+        assert abs(g.max() - 1.148148) < 1e-5 and abs(_amplification(np.pi / 2, np.pi, True) - g.max()) < 1e-12
+        assert max(_amplification(a, 0.0, True) for a in k) <= 1 + 1e-12
+    else:
+        assert g.max() <= 1 + 1e-12
+    n = 32
+    prm = inputs.default_params(n, n)
+    # a vanishing surface tension removes the force sum mu grad C, which would
+    # otherwise couple the velocity to the perturbation at first order
+    prm.update(rho=[1.0, 1.0, 1.0], D0=0.0, variable_mobility=0, sigma12=1e-30, sigma13=1e-30, sigma23=1e-30,
+               hforce_mode=hforce_mode)
+    C = (0.3 + 1e-12 * inputs.uniform(3, n * n, -1, 1).reshape(n, n))[None]
+    o = Oracle(prm)
+    o.init_fields(C)
+    amp = []
+    for _ in range(3):
+        o.step(60)
+        amp.append(np.abs(o.macroscopic()["phi"][0][n // 4: 3 * n // 4] - 0.3).max())
+    rate = (amp[2] / amp[1]) ** (1.0 / 60)
+    if hforce_mode == 0:
+        assert 0.985 * g.max() < rate <= g.max() + 1e-3, rate
+    else:
+        assert rate < 1.0 and amp[2] < 1e-12, (rate, amp)
