@@ -77,14 +77,14 @@
 #include "pfo.h"
 
 /* Per-node loops are split over rows with OpenMP when the library is built
- * with it, for domains of 4096 nodes or more (smaller ones run on the calling
+ * with it, for domains of 2048 nodes or more (smaller ones run on the calling
  * thread: starting a parallel region costs more than such a loop).  Each
  * node is computed by one thread with the same operations, so the results do
  * not depend on the thread count.  (Testing only: speed.)  OMP_FOR is used
  * only where the context `c` is in scope. */
 #ifdef _OPENMP
 #include <omp.h>
-#define OMP_FOR _Pragma("omp parallel for schedule(static) if(c->n >= 4096)")
+#define OMP_FOR _Pragma("omp parallel for schedule(static) if(c->n >= 2048)")
 #else
 #define OMP_FOR
 #endif
@@ -138,6 +138,7 @@ struct pfo_ctx {
     double *gpost;           /* [9][n] */
     double *hpost;           /* [n_h][9][n] */
     double *taunew;          /* [n] */
+    double *gold;            /* [9][n] gbar before streaming (open x only) */
 };
 
 /* ---------------------------------------------------------------- indexing */
@@ -154,9 +155,12 @@ static inline int mirrory(int y, int ny) {
     }
     return y;
 }
-static inline double at(const double *f, int x, int y, int nx, int ny) {
-    return f[mirrory(y, ny) * nx + wrapx(x, nx)];
+/* x is periodic, or with open x (velocity inlet at x = 0, outflow at
+ * x = nx-1) mirrored about x = -1/2 and x = nx - 1/2 like the walls */
+static inline double at(const double *f, int x, int y, int nx, int ny, int ox) {
+    return f[mirrory(y, ny) * nx + (ox ? mirrory(x, nx) : wrapx(x, nx))];
 }
+#define OX (c->p.open_x)
 
 /* ------------------------------------------------------------- stencils (R9)
  * Isotropic central gradient: grad phi = sum_a w_a e_a [phi(x+e_a)-phi(x-e_a)] / (2 c_s^2).
@@ -166,33 +170,33 @@ static inline double at(const double *f, int x, int y, int nx, int ny) {
  *   d_a phi = [-phi(x+2e) + 5 phi(x+e) - 3 phi(x) - phi(x-e)] / 4.
  * Mixed gradient: grad^MD phi = sum_a w_a e_a d_a phi / c_s^2.
  */
-static void grad_cd_at(const double *f, int x, int y, int nx, int ny, double *gx, double *gy) {
+static void grad_cd_at(const double *f, int x, int y, int nx, int ny, int ox, double *gx, double *gy) {
     double sx = 0.0, sy = 0.0;
     for (int a = 1; a < 9; ++a) {
-        double d = at(f, x + EX[a], y + EY[a], nx, ny) - at(f, x - EX[a], y - EY[a], nx, ny);
+        double d = at(f, x + EX[a], y + EY[a], nx, ny, ox) - at(f, x - EX[a], y - EY[a], nx, ny, ox);
         sx += W[a] * EX[a] * d;
         sy += W[a] * EY[a] * d;
     }
     *gx = sx / (2.0 * CS2);
     *gy = sy / (2.0 * CS2);
 }
-static double lap_cd_at(const double *f, int x, int y, int nx, int ny) {
-    double c = at(f, x, y, nx, ny), s = 0.0;
+static double lap_cd_at(const double *f, int x, int y, int nx, int ny, int ox) {
+    double c = at(f, x, y, nx, ny, ox), s = 0.0;
     for (int a = 1; a < 9; ++a)
-        s += W[a] * (at(f, x + EX[a], y + EY[a], nx, ny) - 2.0 * c + at(f, x - EX[a], y - EY[a], nx, ny));
+        s += W[a] * (at(f, x + EX[a], y + EY[a], nx, ny, ox) - 2.0 * c + at(f, x - EX[a], y - EY[a], nx, ny, ox));
     return s / CS2;
 }
-static double dir_md_at(const double *f, int x, int y, int a, int nx, int ny) {
-    return (-at(f, x + 2 * EX[a], y + 2 * EY[a], nx, ny) + 5.0 * at(f, x + EX[a], y + EY[a], nx, ny)
-            - 3.0 * at(f, x, y, nx, ny) - at(f, x - EX[a], y - EY[a], nx, ny)) / 4.0;
+static double dir_md_at(const double *f, int x, int y, int a, int nx, int ny, int ox) {
+    return (-at(f, x + 2 * EX[a], y + 2 * EY[a], nx, ny, ox) + 5.0 * at(f, x + EX[a], y + EY[a], nx, ny, ox)
+            - 3.0 * at(f, x, y, nx, ny, ox) - at(f, x - EX[a], y - EY[a], nx, ny, ox)) / 4.0;
 }
-static double dir_cd_at(const double *f, int x, int y, int a, int nx, int ny) {
-    return (at(f, x + EX[a], y + EY[a], nx, ny) - at(f, x - EX[a], y - EY[a], nx, ny)) / 2.0;
+static double dir_cd_at(const double *f, int x, int y, int a, int nx, int ny, int ox) {
+    return (at(f, x + EX[a], y + EY[a], nx, ny, ox) - at(f, x - EX[a], y - EY[a], nx, ny, ox)) / 2.0;
 }
-static void grad_md_at(const double *f, int x, int y, int nx, int ny, double *gx, double *gy) {
+static void grad_md_at(const double *f, int x, int y, int nx, int ny, int ox, double *gx, double *gy) {
     double sx = 0.0, sy = 0.0;
     for (int a = 1; a < 9; ++a) {
-        double d = dir_md_at(f, x, y, a, nx, ny);
+        double d = dir_md_at(f, x, y, a, nx, ny, ox);
         sx += W[a] * EX[a] * d;
         sy += W[a] * EY[a] * d;
     }
@@ -319,6 +323,7 @@ static void *zalloc(size_t n) { void *q = calloc(n ? n : 1, sizeof(double)); ret
 int pfo_create(const pfo_params *prm, pfo_ctx **out) {
     if (!prm || !out) return -1;
     if (prm->nx < 5 || prm->ny < 5 || (prm->n_h != 1 && prm->n_h != 2)) return -1;
+    if (prm->open_x != 0 && prm->open_x != 1) return -1;
     for (int k = 0; k < 3; ++k) if (!(prm->rho[k] > 0.0)) return -1;
     pfo_ctx *c = (pfo_ctx *)calloc(1, sizeof(pfo_ctx));
     if (!c) return -3;
@@ -331,9 +336,10 @@ int pfo_create(const pfo_params *prm, pfo_ctx **out) {
     c->dif = zalloc(2 * n); c->gradrho = zalloc(2 * n); c->Fs = zalloc(2 * n); c->u = zalloc(2 * n);
     c->pr = zalloc(n); c->gradp = zalloc(2 * n); c->tmp = zalloc(n);
     c->gpost = zalloc(9 * n); c->hpost = zalloc(nh * 9 * n); c->taunew = zalloc(n);
+    c->gold = prm->open_x ? zalloc(9 * n) : NULL;
     if (!c->g || !c->h || !c->tau || !c->C || !c->rho || !c->gradC || !c->lapC || !c->gradM || !c->mu ||
         !c->gradmu || !c->lapmu || !c->dif || !c->gradrho || !c->Fs || !c->u || !c->pr || !c->gradp ||
-        !c->tmp || !c->gpost || !c->hpost || !c->taunew) {
+        !c->tmp || !c->gpost || !c->hpost || !c->taunew || (prm->open_x && !c->gold)) {
         pfo_destroy(c);
         return -3;
     }
@@ -346,7 +352,7 @@ void pfo_destroy(pfo_ctx *c) {
     free(c->g); free(c->h); free(c->tau); free(c->C); free(c->rho); free(c->gradC); free(c->lapC);
     free(c->gradM); free(c->mu); free(c->gradmu); free(c->lapmu); free(c->dif); free(c->gradrho);
     free(c->Fs); free(c->u); free(c->pr); free(c->gradp); free(c->tmp); free(c->gpost); free(c->hpost);
-    free(c->taunew);
+    free(c->taunew); free(c->gold);
     free(c);
 }
 
@@ -382,16 +388,16 @@ static void stage_chem(pfo_ctx *c) {
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 int q = y * nx + x;
-                grad_cd_at(f, x, y, nx, ny, &c->gradC[(2 * k) * n + q], &c->gradC[(2 * k + 1) * n + q]);
-                c->lapC[k * n + q] = lap_cd_at(f, x, y, nx, ny);
-                grad_cd_at(c->tmp, x, y, nx, ny, &c->gradM[(2 * k) * n + q], &c->gradM[(2 * k + 1) * n + q]);
+                grad_cd_at(f, x, y, nx, ny, OX, &c->gradC[(2 * k) * n + q], &c->gradC[(2 * k + 1) * n + q]);
+                c->lapC[k * n + q] = lap_cd_at(f, x, y, nx, ny, OX);
+                grad_cd_at(c->tmp, x, y, nx, ny, OX, &c->gradM[(2 * k) * n + q], &c->gradM[(2 * k + 1) * n + q]);
             }
     }
     OMP_FOR
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int q = y * nx + x;
-            grad_cd_at(c->rho, x, y, nx, ny, &c->gradrho[q], &c->gradrho[n + q]);
+            grad_cd_at(c->rho, x, y, nx, ny, OX, &c->gradrho[q], &c->gradrho[n + q]);
             double ck[3] = {c->C[q], c->C[n + q], c->C[2 * n + q]};
             double lk[3] = {c->lapC[q], c->lapC[n + q], c->lapC[2 * n + q]};
             double m[3];
@@ -412,8 +418,8 @@ static void stage_diffusion(pfo_ctx *c) {
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 int q = y * nx + x;
-                grad_cd_at(f, x, y, nx, ny, &c->gradmu[(2 * k) * n + q], &c->gradmu[(2 * k + 1) * n + q]);
-                c->lapmu[k * n + q] = lap_cd_at(f, x, y, nx, ny);
+                grad_cd_at(f, x, y, nx, ny, OX, &c->gradmu[(2 * k) * n + q], &c->gradmu[(2 * k + 1) * n + q]);
+                c->lapmu[k * n + q] = lap_cd_at(f, x, y, nx, ny, OX);
             }
     }
     for (int i = 0; i < c->p.n_h; ++i) {
@@ -427,8 +433,8 @@ static void stage_diffusion(pfo_ctx *c) {
                     /* conservative link form of div(M grad mu) */
                     double s = 0.0, m0 = mobility(&c->p, S, i, ci[q]);
                     for (int a = 1; a < 9; ++a) {
-                        double m1 = mobility(&c->p, S, i, at(ci, x + EX[a], y + EY[a], nx, ny));
-                        s += W[a] * (m0 + m1) * (at(mi, x + EX[a], y + EY[a], nx, ny) - mi[q]);
+                        double m1 = mobility(&c->p, S, i, at(ci, x + EX[a], y + EY[a], nx, ny, OX));
+                        s += W[a] * (m0 + m1) * (at(mi, x + EX[a], y + EY[a], nx, ny, OX) - mi[q]);
                     }
                     v = s / CS2;
                 } else {
@@ -491,7 +497,7 @@ static void stage_hydro(pfo_ctx *c) {
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int q = y * nx + x;
-            grad_cd_at(c->pr, x, y, nx, ny, &c->gradp[q], &c->gradp[n + q]);
+            grad_cd_at(c->pr, x, y, nx, ny, OX, &c->gradp[q], &c->gradp[n + q]);
         }
 }
 
@@ -549,11 +555,11 @@ static void stage_collide(pfo_ctx *c) {
                     for (int k = 0; k < 3; ++k) dC[a][k] = EX[a] * gcx[k] + EY[a] * gcy[k];
                 }
             } else {
-                grad_md_at(c->rho, x, y, nx, ny, &gmdx, &gmdy);
-                for (int k = 0; k < 3; ++k) grad_md_at(c->C + (size_t)k * n, x, y, nx, ny, &gcx[k], &gcy[k]);
+                grad_md_at(c->rho, x, y, nx, ny, OX, &gmdx, &gmdy);
+                for (int k = 0; k < 3; ++k) grad_md_at(c->C + (size_t)k * n, x, y, nx, ny, OX, &gcx[k], &gcy[k]);
                 for (int a = 0; a < 9; ++a) {
-                    drho[a] = dir_md_at(c->rho, x, y, a, nx, ny);
-                    for (int k = 0; k < 3; ++k) dC[a][k] = dir_md_at(c->C + (size_t)k * n, x, y, a, nx, ny);
+                    drho[a] = dir_md_at(c->rho, x, y, a, nx, ny, OX);
+                    for (int k = 0; k < 3; ++k) dC[a][k] = dir_md_at(c->C + (size_t)k * n, x, y, a, nx, ny, OX);
                 }
             }
 
@@ -573,8 +579,8 @@ static void stage_collide(pfo_ctx *c) {
                             gmx = c->gradmu[(2 * k) * n + q]; gmy = c->gradmu[(2 * k + 1) * n + q];
                             dm = EX[a] * gmx + EY[a] * gmy;
                         } else {
-                            dm = dir_md_at(c->mu + (size_t)k * n, x, y, a, nx, ny);
-                            grad_md_at(c->mu + (size_t)k * n, x, y, nx, ny, &gmx, &gmy);
+                            dm = dir_md_at(c->mu + (size_t)k * n, x, y, a, nx, ny, OX);
+                            grad_md_at(c->mu + (size_t)k * n, x, y, nx, ny, OX, &gmx, &gmy);
                         }
                         t2 -= ck[k] * (dm - (m.ux * gmx + m.uy * gmy));
                     }
@@ -600,8 +606,8 @@ static void stage_collide(pfo_ctx *c) {
             double bx = c->gradp[q] - m.Fx, by = c->gradp[n + q] - m.Fy; /* grad p - sum mu grad C - F_b */
             double dp[9], gpx = 0.0, gpy = 0.0;
             if (P->hforce_mode == 2) {
-                grad_md_at(c->pr, x, y, nx, ny, &gpx, &gpy);
-                for (int a = 0; a < 9; ++a) dp[a] = dir_md_at(c->pr, x, y, a, nx, ny);
+                grad_md_at(c->pr, x, y, nx, ny, OX, &gpx, &gpy);
+                for (int a = 0; a < 9; ++a) dp[a] = dir_md_at(c->pr, x, y, a, nx, ny, OX);
             }
             for (int i = 0; i < nh; ++i) {
                 double cc = ck[i];
@@ -627,27 +633,122 @@ static void stage_collide(pfo_ctx *c) {
         }
 }
 
+/* Streamed value of population a at node (x, y) in the interior rule:
+ * periodic (or, with open x, any source inside the domain), half-way
+ * bounce-back when the source lies beyond a wall (R15). */
+static double streamed_g(const pfo_ctx *c, int a, int x, int y) {
+    int sy = y - EY[a], sx = x - EX[a], n = c->n;
+    if (sy < 0 || sy >= c->ny) return c->gpost[(size_t)OPP[a] * n + y * c->nx + x];
+    return c->gpost[(size_t)a * n + sy * c->nx + wrapx(sx, c->nx)];
+}
+static double streamed_h(const pfo_ctx *c, int i, int a, int x, int y) {
+    int sy = y - EY[a], sx = x - EX[a], n = c->n;
+    if (sy < 0 || sy >= c->ny) return c->hpost[((size_t)i * 9 + OPP[a]) * n + y * c->nx + x];
+    return c->hpost[((size_t)i * 9 + a) * n + sy * c->nx + wrapx(sx, c->nx)];
+}
+
+/* Open x (Sec. 3.2: velocity inlet on the left, convective outflow on the
+ * right; the paper cites these conditions without printing them, so they
+ * are derived here for the transformed populations).  A population whose
+ * source lies beyond a wall is bounced back first (R15); the others whose
+ * source lies beyond x = 0 or x = nx-1 are set here.
+ *   Inlet (x = 0; pure component 3 flows in with u = (u_in, 0)): every
+ *   unknown a (e_ax = +1) takes gbar_a = gbar_abar + gbar_eq,a - gbar_eq,abar,
+ *   the odd part of the equilibrium at u_in (the node's density,
+ *   grad rho = 0, the body force as the only force).  That makes
+ *   sum_a e_ax gbar_a = c_s^2 (rho u_in - F_x / 2), so the next velocity
+ *   moment returns u_in; with both diagonals unknown, the pair 5 / 8 shares
+ *   a correction that sets sum_a e_ay gbar_a = -c_s^2 F_y / 2 as well (the
+ *   Zou-He non-equilibrium bounce-back); at a corner, where one diagonal
+ *   comes from the wall, the other diagonal and the axis population take
+ *   the corrections that meet both components.  The unknown hbar_a are 0 plus the receiving node's diffusion
+ *   half (no component 1 or 2 enters).
+ *   Outflow (x = nx-1): the unknown a (e_ax = -1) follow the convective
+ *   condition d/dt + U d/dx = 0, discretised as
+ *   gbar_a(t+1) = [gbar_a(t) + U gbar_a(x-1, t+1)] / (1 + U), U the node's
+ *   u_x at time t (not below 0), with their pressure part w_a p replaced:
+ *   w_a [p_e - (p(x, t) + U p(x-1, t)) / (1 + U)] is added, p_e = 2 p(x-1, t)
+ *   - p(x-2, t) the linear extrapolation of the pressure.  (Applied to the
+ *   whole population, the convective condition also transports the pressure,
+ *   dp/dt = -U dp/dx, which in a developed channel flow with its constant
+ *   pressure drop makes the pressure, and the mass held by the weakly
+ *   compressible lattice, grow without bound while less leaves than enters.)
+ *   hbar_a copies its neighbour's new value (zero normal gradient). */
+static void open_x_columns(pfo_ctx *c) {
+    int nx = c->nx, ny = c->ny, n = c->n, nh = c->p.n_h;
+    const pfo_params *P = &c->p;
+    for (int y = 0; y < ny; ++y) {
+        /* inlet */
+        int q = y * nx;
+        double rho = c->rho[q];
+        node_macro m = {P->u_in, 0.0, rho, 0.0, 0.0, 0.0, rho * P->fx, -rho * P->g};
+        double g[9];
+        int unknown[9] = {0};
+        for (int a = 0; a < 9; ++a) {
+            int sy = y - EY[a];
+            g[a] = c->g[(size_t)a * n + q];      /* already streamed (interior rule) */
+            if (EX[a] == 1 && sy >= 0 && sy < ny) unknown[a] = 1;
+        }
+        for (int a = 0; a < 9; ++a)
+            if (unknown[a]) g[a] = g[OPP[a]] + gbar_eq(&m, a) - gbar_eq(&m, OPP[a]);
+        double jx = (rho * P->u_in - 0.5 * m.Fx) * CS2, jy = (0.0 - 0.5 * m.Fy) * CS2;
+        double rx = jx, ry = jy;
+        for (int a = 0; a < 9; ++a) { rx -= EX[a] * g[a]; ry -= EY[a] * g[a]; }
+        if (unknown[5] && unknown[8]) {
+            /* the pair shares the y correction (x unchanged); rx is 0 up to rounding */
+            g[5] += 0.5 * ry;
+            g[8] -= 0.5 * ry;
+            g[1] += rx;
+        } else {
+            /* a corner: one diagonal comes from the wall, the other (d) and the
+             * axis population meet both components */
+            int d = unknown[5] ? 5 : 8;
+            g[d] += EY[d] * ry;
+            g[1] += rx - EY[d] * ry;
+        }
+        for (int a = 0; a < 9; ++a) c->g[(size_t)a * n + q] = g[a];
+        for (int i = 0; i < nh; ++i)
+            for (int a = 0; a < 9; ++a)
+                if (unknown[a])
+                    c->h[((size_t)i * 9 + a) * n + q] = 0.5 * c->dif[i * n + q] * Gamma(a, c->u[q], c->u[n + q]);
+        /* outflow */
+        q = y * nx + nx - 1;
+        int qn = q - 1;
+        double U = c->u[q] > 0.0 ? c->u[q] : 0.0;
+        double pt = 2.0 * c->pr[qn] - c->pr[qn - 1];   /* linear extrapolation of p at time t */
+        for (int a = 0; a < 9; ++a) {
+            int sy = y - EY[a];
+            if (EX[a] != -1 || sy < 0 || sy >= ny) continue;
+            double gnext = streamed_g(c, a, nx - 2, y);
+            c->g[(size_t)a * n + q] = (c->gold[(size_t)a * n + q] + U * gnext) / (1.0 + U)
+                                      + W[a] * (pt - (c->pr[q] + U * c->pr[qn]) / (1.0 + U));
+            for (int i = 0; i < nh; ++i)
+                c->h[((size_t)i * 9 + a) * n + q] = streamed_h(c, i, a, nx - 2, y)
+                    + 0.5 * c->dif[i * n + qn] * Gamma(a, c->u[qn], c->u[n + qn]);
+        }
+    }
+}
+
 /* Stage 12-13: streaming (periodic x, half-way bounce-back in y, R15) and the
- * receiving-node half of the diffusion term (R12). */
+ * receiving-node half of the diffusion term (R12); with open x the boundary
+ * columns are completed by open_x_columns. */
 static void stage_stream(pfo_ctx *c) {
     int nx = c->nx, ny = c->ny, n = c->n, nh = c->p.n_h;
+    if (OX) memcpy(c->gold, c->g, sizeof(double) * 9 * (size_t)n);
     OMP_FOR
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int q = y * nx + x;
             double ux = c->u[q], uy = c->u[n + q];
             for (int a = 0; a < 9; ++a) {
-                int sy = y - EY[a];
-                int sq, sa;
-                if (sy < 0 || sy >= ny) { sq = q; sa = OPP[a]; }
-                else { sq = sy * nx + wrapx(x - EX[a], nx); sa = a; }
-                c->g[(size_t)a * n + q] = c->gpost[(size_t)sa * n + sq];
+                c->g[(size_t)a * n + q] = streamed_g(c, a, x, y);
                 double G = Gamma(a, ux, uy);
                 for (int i = 0; i < nh; ++i)
-                    c->h[((size_t)i * 9 + a) * n + q] = c->hpost[((size_t)i * 9 + sa) * n + sq] + 0.5 * c->dif[i * n + q] * G;
+                    c->h[((size_t)i * 9 + a) * n + q] = streamed_h(c, i, a, x, y) + 0.5 * c->dif[i * n + q] * G;
             }
             c->tau[q] = c->taunew[q];
         }
+    if (OX) open_x_columns(c);
 }
 
 static void macro_from_state(pfo_ctx *c) {
@@ -695,7 +796,7 @@ int pfo_init_fields(pfo_ctx *c, const double *C, const double *u, const double *
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int q = y * nx + x;
-            grad_cd_at(c->pr, x, y, nx, ny, &c->gradp[q], &c->gradp[n + q]);
+            grad_cd_at(c->pr, x, y, nx, ny, OX, &c->gradp[q], &c->gradp[n + q]);
         }
     for (int q = 0; q < n; ++q) {
         node_macro m = {c->u[q], c->u[n + q], c->rho[q], c->pr[q], c->gradrho[q], c->gradrho[n + q],
@@ -819,11 +920,11 @@ int pfo_stencil(const double *f, int nx, int ny, int kind, int a, double *out) {
         for (int x = 0; x < nx; ++x) {
             int q = y * nx + x;
             switch (kind) {
-                case 0: grad_cd_at(f, x, y, nx, ny, &out[q], &out[n + q]); break;
-                case 1: out[q] = lap_cd_at(f, x, y, nx, ny); break;
-                case 2: out[q] = dir_md_at(f, x, y, a, nx, ny); break;
-                case 3: grad_md_at(f, x, y, nx, ny, &out[q], &out[n + q]); break;
-                case 4: out[q] = dir_cd_at(f, x, y, a, nx, ny); break;
+                case 0: grad_cd_at(f, x, y, nx, ny, 0, &out[q], &out[n + q]); break;
+                case 1: out[q] = lap_cd_at(f, x, y, nx, ny, 0); break;
+                case 2: out[q] = dir_md_at(f, x, y, a, nx, ny, 0); break;
+                case 3: grad_md_at(f, x, y, nx, ny, 0, &out[q], &out[n + q]); break;
+                case 4: out[q] = dir_cd_at(f, x, y, a, nx, ny, 0); break;
                 default: return -1;
             }
         }

@@ -37,6 +37,8 @@ typedef struct {
     int32_t force_potential;
     int32_t mix_linear;
     int32_t tau_iterations;    /* 0: previous-step tau (R7); m: m fixed-point passes */
+    int32_t open_x;            /* 0: x periodic; 1: velocity inlet at x = 0, convective outflow at x = nx-1 */
+    double u_in;               /* inlet velocity along x (open_x = 1) */
 } pfo_params;
 
 typedef struct pfo_ctx pfo_ctx;

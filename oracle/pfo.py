@@ -41,6 +41,7 @@ class Params(ct.Structure):
         ("hforce_mode", ct.c_int32), ("gforce_cd", ct.c_int32),
         ("force_potential", ct.c_int32), ("mix_linear", ct.c_int32),
         ("tau_iterations", ct.c_int32),
+        ("open_x", ct.c_int32), ("u_in", ct.c_double),
     ]
 
 

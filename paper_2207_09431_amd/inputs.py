@@ -115,7 +115,7 @@ def default_params(nx: int, ny: int) -> dict:
         sigma12=1e-3, sigma13=1e-3, sigma23=1e-3, Lambda=0.0,
         xi=4.0, D0=4.0 / 300.0, variable_mobility=1,
         tau_h=0.5, g=0.0, fx=0.0,
-        storage=0, store_h=0, hforce_cd=0,
+        storage=0, store_h=0, hforce_cd=0, open_x=0, u_in=0.0,
     )
 
 
@@ -417,6 +417,26 @@ def channel(n: float, ny: int = 32, nx: int = 5, fx: float = 1e-6, K: float = 0.
                K=K, n=n, nu_min=nu_min, nu_max=nu_max, g=0.0, fx=fx)
     C = np.zeros((1, ny, nx))
     return _case(prm, C, None, None, f"channel_n{n}")
+
+
+def channel_inlet(n: float, nx: int = 240, ny: int = 60, u_in: float = 0.1, nu_wall: float = 0.2,
+                  nu_min: float = 1e-3, nu_max: float = 5.0) -> dict:
+    """The single-phase power-law channel of Sec. 3.2 (Table 2): length nx
+    along x with a velocity inlet u_in at x = 0 and a convective outflow at
+    x = nx - 1, walls at rest below and above (width ny), the liquid
+    (component 3) everywhere, no body force.  The paper gives no consistency
+    K or truncation; here K makes the viscosity at the wall of the developed
+    profile nu_wall, K = nu_wall / gdot_w^(n-1) with the developed wall shear
+    rate gdot_w = u_in (2n+1) / (n L), L = ny/2, and nu is limited to
+    [nu_min, nu_max], outside most of the profile."""
+    prm = default_params(nx, ny)
+    L = ny / 2.0
+    gw = u_in * (2.0 * n + 1.0) / (n * L)
+    K = nu_wall / gw ** (n - 1.0)
+    prm.update(rho=[1.0, 1.0, 1.0], nu=[1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0], powerlaw_comp=2,
+               K=K, n=n, nu_min=nu_min, nu_max=nu_max, g=0.0, fx=0.0, open_x=1, u_in=u_in)
+    C = np.zeros((1, ny, nx))
+    return _case(prm, C, None, None, f"channel_inlet_n{n}_{nx}x{ny}")
 
 
 def layered_flow(n3: float, lam: float, ny: int = 200, nx: int = 5, nu1: float = 1.0 / 6.0,
