@@ -78,6 +78,17 @@ typedef struct {
                                   assigning them to terms.  With variable mobility (Eq. (6)) use 1:
                                   in a phase where D_i vanishes the mixed form amplifies oblique
                                   modes (up to 1.148 per step), the central form does not */
+    int32_t open_x;            /* 0: x periodic.  1: velocity inlet at x = 0 and convective outflow at
+                                  x = nx-1 (Sec. 3.2; compact state forms only, store_h = 0).  The
+                                  inlet brings pure component 3 in with u = (u_in, 0): the unknown
+                                  gbar take the odd part of the equilibrium at u_in plus the
+                                  corrections that make both velocity moments exact, the unknown
+                                  hbar carry no component 1 or 2.  The outflow applies
+                                  d/dt + U d/dx = 0 (U the node's u_x, not below 0) to the unknown
+                                  gbar with their pressure part replaced by the linear
+                                  extrapolation of p, and copies the neighbour's hbar.  Stencil
+                                  ghosts beyond the ends mirror the end columns */
+    double u_in;               /* inlet velocity (open_x = 1) */
 } pflbm_params;
 
 /*
@@ -113,9 +124,10 @@ size_t pflbm_workspace_bytes(const pflbm_params* cases, int32_t ncases);
  * (nx or ny < 5, n_h not 1 or 2, rho_k <= 0, nu_k <= 0, nu_min <= 0 or
  * nu_min > nu_max, K <= 0 with a power-law component, xi <= 0, D0 < 0,
  * tau_h <= 0, a Sigma_i <= 0, store_h = 0 with tau_h != 0.5, storage not
- * 0 or 1, tau_iterations outside 0..8, hforce_cd not 0 or 1, nx rounded up
- * to 64 times ny at or above 2^29 nodes);
- * UNSUPPORTED for storage = 1 with store_h = 1; WORKSPACE when the
+ * 0 or 1, tau_iterations outside 0..8, hforce_cd or open_x not 0 or 1, a
+ * non-finite u_in with open_x, nx rounded up to 64 times ny at or above 2^29
+ * nodes);
+ * UNSUPPORTED for storage = 1 with store_h = 1, or open_x with store_h = 1; WORKSPACE when the
  * workspace is NULL, small or misaligned; DEVICE when a HIP call fails.
  */
 int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspace, size_t bytes,

@@ -35,7 +35,8 @@ __device__ __forceinline__ NodeStencil stencil_at(const CaseDev& cd, int x, int 
     float f1[9], f2[9], r[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        get(wrap_x(x + Lat::ex[a], cd.nx), mirror_y(y + Lat::ey[a], cd.ny), q1[a], q2[a]);
+        const int xa = x + Lat::ex[a];
+        get(cd.openx ? mirror_y(xa, cd.nx) : wrap_x(xa, cd.nx), mirror_y(y + Lat::ey[a], cd.ny), q1[a], q2[a]);
         f1[a] = (float)q1[a];
         f2[a] = (float)q2[a];
         r[a] = mix_rho(cd, q1[a], q2[a]);
@@ -117,8 +118,9 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const CaseDev* __restrict_
     if (pin) {
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            const double pp = pin[(long long)mirror_y(y + Lat::ey[a], ny) * nx + wrap_x(x + Lat::ex[a], nx)];
-            const double pm = pin[(long long)mirror_y(y - Lat::ey[a], ny) * nx + wrap_x(x - Lat::ex[a], nx)];
+            const int xp = x + Lat::ex[a], xm = x - Lat::ex[a];
+            const double pp = pin[(long long)mirror_y(y + Lat::ey[a], ny) * nx + (cd.openx ? mirror_y(xp, nx) : wrap_x(xp, nx))];
+            const double pm = pin[(long long)mirror_y(y - Lat::ey[a], ny) * nx + (cd.openx ? mirror_y(xm, nx) : wrap_x(xm, nx))];
             const float dp = (float)(pp - pm);
             gpx += Lat::w[a] * Lat::ex[a] * dp;
             gpy += Lat::w[a] * Lat::ey[a] * dp;

@@ -52,6 +52,8 @@ struct CaseDev {
     int vm;             // variable mobility
     int tau_iters;      // fixed-point passes of the implicit tau (0: previous step's tau)
     int hcd;            // central differences for grad C_i in the hbar forcing
+    int openx;          // velocity inlet at x = 0 and outflow at x = nx-1 (else x periodic)
+    float u_in;         // inlet velocity
     float K, nexp, numin, numax;
     float sig12, sig13, sig23, lam;
     float Sig[3];

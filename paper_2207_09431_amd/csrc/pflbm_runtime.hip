@@ -98,6 +98,8 @@ bool valid_params(const pflbm_params& p) {
     if (!p.store_h && p.tau_h != 0.5) return false;
     if (p.tau_iterations < 0 || p.tau_iterations > 8) return false;
     if (p.hforce_cd != 0 && p.hforce_cd != 1) return false;
+    if (p.open_x != 0 && p.open_x != 1) return false;
+    if (p.open_x && !is_finite(p.u_in)) return false;
     return true;
 }
 
@@ -269,6 +271,9 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
     Layout L;
     if (!cases || ncases <= 0 || !make_layout(cases, ncases, &L)) return PFLBM_ERR_INVALID_ARG;
     if (cases[0].storage == 1 && cases[0].store_h) return PFLBM_ERR_UNSUPPORTED;
+    // open ends are built for the compact state forms only
+    for (int k = 0; k < ncases; ++k)
+        if (cases[k].open_x && cases[k].store_h) return PFLBM_ERR_UNSUPPORTED;
     if (!d_workspace || bytes < L.total || ((uintptr_t)d_workspace % kAlign) != 0) return PFLBM_ERR_WORKSPACE;
     pflbm_ctx* c = new (std::nothrow) pflbm_ctx;
     if (!c) return PFLBM_ERR_DEVICE;
@@ -303,6 +308,8 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
         d.vm = p.variable_mobility ? 1 : 0;
         d.tau_iters = p.tau_iterations;
         d.hcd = p.hforce_cd;
+        d.openx = p.open_x;
+        d.u_in = (float)p.u_in;
         d.K = (float)p.K; d.nexp = (float)p.n; d.numin = (float)p.nu_min; d.numax = (float)p.nu_max;
         d.sig12 = (float)p.sigma12; d.sig13 = (float)p.sigma13; d.sig23 = (float)p.sigma23; d.lam = (float)p.Lambda;
         double S[3], ST;

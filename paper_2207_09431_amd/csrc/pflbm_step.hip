@@ -169,6 +169,10 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     _Float16* Qout = cd.Q[par ^ 1];
     const float qinv = cd.qinv, qscale = cd.qscale;
     const int tid = threadIdx.x;
+    // open x (velocity inlet at x = 0, outflow at x = nx-1): stencil ghosts
+    // mirror in x like the walls' rows, and the boundary columns are
+    // completed in phase D
+    const bool openx = cd.openx != 0;
 
     // ---------------- phase A: C_i and rho on R3
     // All global loads of phases A and B are issued here, phase A's first, so
@@ -189,7 +193,8 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         constexpr bool PLAIN = decltype(plain_tag)::value;
         auto node = [&](int rx, int ry, int h) -> uint32_t {
             if (PLAIN) return (uint32_t)((y0 - h + ry) * pitch + (x0 - h + rx));
-            return (uint32_t)(mirror_y(y0 - h + ry, ny) * pitch + wrap_x_tile(x0 - h + rx, nx));
+            const int xr = x0 - h + rx;
+            return (uint32_t)(mirror_y(y0 - h + ry, ny) * pitch + (openx ? mirror_y(xr, nx) : wrap_x_tile(xr, nx)));
         };
 #pragma unroll
         for (int k = 0; k < KA; ++k) {
@@ -315,6 +320,17 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         }
     }
     __syncthreads();
+    // with open x the two ghost columns beyond each end mirror the end
+    // columns for grad p (same row: no reference difference)
+    if (openx && (x0 < 2 || x0 + TX + 2 > nx)) {
+        for (int idx = tid; idx < N2; idx += NT) {
+            const int ry = idx / W2, rx = idx - ry * W2;
+            const int gxr = x0 - 2 + rx, gyr = y0 - 2 + ry;
+            if ((gxr < 0 || (gxr >= nx && gxr < nx + 2)) && gyr >= 0 && gyr < ny)
+                sP[idx] = sP[ry * W2 + (mirror_y(gxr, nx) - (x0 - 2))];
+        }
+        __syncthreads();
+    }
     // the two ghost rows beyond each wall mirror the wall rows for grad p
     // (rows farther out are never read); only tiles next to a wall have them
     if (y0 < 2 || y0 + TY + 2 > ny) {
@@ -336,6 +352,8 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const int idx = region_node<TX, 1>(n, H1, rx, ry);
         const int gyr = y0 - 1 + ry;
         if (gyr < 0 || gyr >= ny) continue;   // nodes beyond the walls are never sources
+        // nor, with open x, nodes beyond the ends (their populations are replaced)
+        if (openx && (x0 - 1 + rx < 0 || x0 - 1 + rx >= nx)) continue;
         const int i2 = (ry + 1) * W2 + rx + 1;
         const int i3 = (ry + 2) * W3 + rx + 2;
 
@@ -563,6 +581,81 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
                 if (!bb[a] && Lat::ey[a] != 0) sv += Lat::ey[a] > 0 ? pg : -pg;
                 ds[a] = (float)sv;
                 dv[a] = sD[dir[a]][src[a]];
+            }
+            // region index of the output node on R3
+            const int j3 = (oy + 3) * W3 + ox + 3;
+            // open ends: populations whose source lies beyond x = 0 or nx-1
+            // (and not beyond a wall) are set by the inlet or outflow condition
+            const bool inlet = WALL && openx && gx == 0, outlet = WALL && openx && gx == nx - 1;
+            bool unk[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) unk[a] = (inlet && Lat::ex[a] == 1 && !bb[a]) || (outlet && Lat::ex[a] == -1 && !bb[a]);
+            if (inlet) {
+                // velocity inlet, pure component 3 entering with u = (u_in, 0):
+                // gbar_a = gbar_abar + (gbar_eq,a - gbar_eq,abar) at u_in (grad rho = 0,
+                // the body force as the force), then corrections that make both
+                // velocity moments exact
+                const float rho = sR[j3], Fx = rho * cd.fx, Fy = -rho * cd.g, ui = cd.u_in;
+                float mx = 0.f, my = 0.f;
+#pragma unroll
+                for (int a = 0; a < 9; ++a) {
+                    if (unk[a]) {
+                        const int b = Lat::opp[a];
+                        const float eu = Lat::ex[a] * ui, eF = edot(Lat::ex[a], Lat::ey[a], Fx, Fy);
+                        const float odd = 2.0f * rho * eu - eF * (1.0f + 4.5f * eu * eu - 1.5f * ui * ui) + 3.0f * (ui * Fx) * eu;
+                        ds[a] = ds[b];
+                        dv[a] = dv[b] + Lat::w[a] * odd;
+                    }
+                }
+#pragma unroll
+                for (int a = 1; a < 9; ++a) {
+                    const float v = fmaf(Lat::w[a], ds[a], dv[a]);
+                    mx += Lat::ex[a] * v;
+                    my += Lat::ey[a] * v;
+                }
+                const float rx_ = kCs2 * (rho * ui - 0.5f * Fx) - mx, ry_ = kCs2 * (-0.5f * Fy) - my;
+                if (unk[5] && unk[8]) {
+                    dv[5] += 0.5f * ry_;
+                    dv[8] -= 0.5f * ry_;
+                    dv[1] += rx_;
+                } else {
+                    const int d = unk[5] ? 5 : 8;
+                    dv[d] += Lat::ey[d] * ry_;
+                    dv[1] += rx_ - Lat::ey[d] * ry_;
+                }
+            } else if (outlet) {
+                // convective outflow on the unknown populations, their pressure
+                // part replaced by the linear extrapolation of p:
+                // gbar_a = [gbar_a(t) + U gbar_a(x-1, t+1)] / (1 + U)
+                //          + w_a [p_e - (p(x, t) + U p(x-1, t)) / (1 + U)]
+                const float U = fmaxf(sUx[i2], 0.0f), iu = 1.0f / (1.0f + U);
+                float dold[9];
+                if (F16) {
+                    float m[kQPlanes];
+#pragma unroll
+                    for (int q = 0; q < kQPlanes; ++q) m[q] = (float)gld(Qin + q * plane, eo * 2u) * qinv;
+                    unpack_devs(gld(Sin, eo * 4u), gld(Sin + plane, eo * 4u), m, dold);
+                } else {
+#pragma unroll
+                    for (int a = 1; a < 9; ++a) dold[a] = gld(Sin + (a - 1) * plane, eo * 4u);
+                }
+                const float pcorr = (2.0f * sP[i2 - 1] - sP[i2 - 2]) - (sP[i2] + U * sP[i2 - 1]) * iu;
+#pragma unroll
+                for (int a = 1; a < 9; ++a) {
+                    if (unk[a]) {
+                        // the neighbour x-1 receives population a from (x, y - e_ay)
+                        const int s2 = i1 - Lat::ey[a] * W1;
+                        double sv = sS[s2] - sy0;
+                        if (Lat::ey[a] != 0) sv += Lat::ey[a] > 0 ? pg : -pg;
+                        const float ds2 = (float)sv;
+                        const float g2 = fmaf(Lat::w[a], ds2, sD[a][s2]);
+                        ds[a] = 0.0f;
+                        dv[a] = fmaf(Lat::w[a], pcorr, (dold[a] + U * g2) * iu);
+                    }
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
                 if (a > 0 && !bb[a]) ssum += Lat::w[a] * ds[a];
                 dsum += dv[a];
             }
@@ -585,12 +678,38 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
                 for (int a = 1; a < 9; ++a) gst(Sout + (a - 1) * plane, eo * 4u, da[a]);
             }
 
-            // region index of the output node and of each source on R3 (for C)
-            const int j3 = (oy + 3) * W3 + ox + 3;
 #pragma unroll
             for (int i = 0; i < NH; ++i) {
                 const float hd = 0.5f * sDif[i][i1];
-                if (SH) {
+                if (!SH && (inlet || outlet)) {
+                    // open ends: an entering population carries no component 1 or
+                    // 2 (only the receiving node's diffusion half, which the hd
+                    // below adds); a leaving one copies its neighbour x-1's new
+                    // value (zero normal gradient)
+                    const double cy = sCd[i][j3];
+                    const float ux = sUx[i2], uy = sUy[i2], uu = ux * ux + uy * uy;
+                    const float nxu = sUx[i2 - 1], nyu = sUy[i2 - 1], nuu = nxu * nxu + nyu * nyu;
+                    const float nhd = 0.5f * sDif[i][i1 - 1];
+                    double dsum = 0.0;
+                    float qsum = 0.f;
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) {
+                        if (unk[a] && inlet) {
+                            dsum -= (double)Lat::w[a] * cy;
+                        } else if (unk[a]) {
+                            const float eu = Lat::ex[a] * ux + Lat::ey[a] * uy, neu = Lat::ex[a] * nxu + Lat::ey[a] * nyu;
+                            const float G = Lat::w[a] * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
+                            const float nG = Lat::w[a] * (1.0f + 3.0f * neu + 4.5f * neu * neu - 1.5f * nuu);
+                            dsum += (double)Lat::w[a] * (sCd[i][j3 - Lat::ey[a] * W3] - cy);
+                            qsum += sH[i][a][i1 - Lat::ey[a] * W1] + (nhd * nG - hd * G);
+                        } else {
+                            qsum += sH[i][dir[a]][src[a]];
+                            if (a > 0 && !bb[a])
+                                dsum += (double)Lat::w[a] * (sCd[i][j3 - Lat::ey[a] * W3 - Lat::ex[a]] - cy);
+                        }
+                    }
+                    gst(Cout + i * plane, eo * 8u, cy + (dsum + (double)(qsum + hd)));
+                } else if (SH) {
                     // hbar_a(y) = w_a C(z_a) + (1 - omega_h) q_b(z_a) + Q_b(z_a) + Dif(y)/2 Gamma_a(y);
                     // C(t+1) = sum_a hbar_a(y) accumulated in float64 around C(y), and the
                     // new deviations q_a = hbar_a - w_a C(t+1)
@@ -631,7 +750,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             }
         }
     };
-    if (y0 == 0 || y0 + TY >= ny) phase_d(std::true_type{});
+    if (y0 == 0 || y0 + TY >= ny || (openx && (x0 == 0 || x0 + TX >= nx))) phase_d(std::true_type{});
     else phase_d(std::false_type{});
 }
 

@@ -1,0 +1,83 @@
+"""The power-law channel of Sec. 3.2 (Table 2) on the GPU: velocity inlet
+u_in = 0.1 at x = 0, convective outflow at x = nx - 1, walls at rest, the
+paper's 60 x 240 lattice (width 60, length 240).
+
+- Parity with the FP64 oracle while the flow develops (2,000 steps): the
+  boundary columns are rebuilt every step, so this is where a mistake in
+  them would show.
+- The steady profile at 3/4 of the length against the developed power-law
+  profile of Eq. (34), within the relative L2 errors of Table 2
+  (tests/golden/table2_channel_erel.json), for the five indices; the flux
+  through every column equals the inflow.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle.pfo import run_case
+from paper_2207_09431_amd import inputs
+from helpers import max_norms, rel_l2
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table2_channel_erel.json")
+
+
+@pytest.fixture(scope="module")
+def Solver():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2207_09431_amd.pflbm import Solver as S
+    return S
+
+
+def developed(y, n, L, u_in):
+    return u_in * (2 * n + 1) / (n + 1) * (1 - np.abs(y / L) ** ((n + 1) / n))
+
+
+def fields(s):
+    m = s.macroscopic(0)
+    s.synchronize()
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in m.items()}
+
+
+@pytest.mark.parametrize("n", [0.5, 1.5])
+def test_channel_parity_while_developing(Solver, n):
+    case = inputs.channel_inlet(n)
+    print(f"case {case['name']}", flush=True)
+    s = Solver(case["params"])
+    s.init_fields(0, case["C"])
+    s.step(2000)
+    m = fields(s)
+    o = run_case(case, 2000).macroscopic()
+    ru, rp = rel_l2(m["u"], o["u"]), rel_l2(m["p"], o["p"])
+    mu, _ = max_norms(m, o)
+    print(f"rel-L2 u {ru:.2e} p {rp:.2e} max u {mu:.2e}", flush=True)
+    assert ru <= 1e-5 and mu <= 1e-4 and rp <= 1e-5
+    assert np.abs(m["phi"]).max() == 0.0
+
+
+def test_channel_matches_table2(Solver):
+    ref = json.load(open(GOLDEN))
+    cases = [inputs.channel_inlet(n) for n in ref["n"]]
+    s = Solver([c["params"] for c in cases])          # the five indices in one batched launch
+    for k, c in enumerate(cases):
+        s.init_fields(k, c["C"])
+    s.step(30000)
+    s.check_state()
+    ny, nx, u_in = 60, 240, 0.1
+    L = ny / 2.0
+    y = np.arange(ny) + 0.5 - L
+    for k, (n, bound) in enumerate(zip(ref["n"], ref["E_rel"])):
+        m = s.macroscopic(k)
+        s.synchronize()
+        ux = m["u"][0].cpu().numpy().astype(np.float64)
+        an = developed(y, n, L, u_in)
+        err = np.linalg.norm(ux[:, 3 * nx // 4] - an) / np.linalg.norm(an)
+        flux = ux.sum(axis=0) / (u_in * ny)
+        print(f"n = {n}: E_rel {err:.4f} (Table 2: {bound}), flux {flux.min():.6f}-{flux.max():.6f}", flush=True)
+        assert err < bound
+        assert np.abs(flux - 1.0).max() < 1e-4
+        assert np.abs(ux[:, 0] - u_in).max() < 1e-6
