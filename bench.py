@@ -28,6 +28,15 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {"source_sha256": "b93a75b291264bae", "variant": "tile32x16_t512",
                     "nx": 2048, "ny": 4096, "bytes_per_launch": 899.7e6}
 
+# VALU instructions per lattice update of the same kernel (rocprofv3
+# SQ_INSTS_VALU / SQ_WAVES: one wave per 64 updates, halo work included),
+# under the same conditions as MEASURED_TRAFFIC.  The VALU issue ceiling of
+# MI355X without packed float32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz =
+# 39.3 T lane-instructions/s.
+MEASURED_VALU = {"source_sha256": "b93a75b291264bae", "variant": "tile32x16_t512",
+                 "nx": 2048, "ny": 4096, "instr_per_update": 1031.0}
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -57,8 +66,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(variant, nx, ny, storage=0):
-    m = MEASURED_TRAFFIC
+def measured_for(m, key, variant, nx, ny, storage=0):
+    """A stored profiler figure if it was taken on these kernel sources,
+    this variant and domain (float32 form), else None."""
     if storage != 0:
         return None
     try:
@@ -66,8 +76,12 @@ def measured_traffic(variant, nx, ny, storage=0):
     except OSError:
         same = False
     if same and variant == m["variant"] and (nx, ny) == (m["nx"], m["ny"]):
-        return m["bytes_per_launch"]
+        return m[key]
     return None
+
+
+def measured_traffic(variant, nx, ny, storage=0):
+    return measured_for(MEASURED_TRAFFIC, "bytes_per_launch", variant, nx, ny, storage)
 
 
 def copy_bandwidth(torch, mib=1024, reps=10):
@@ -251,11 +265,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": f"{case['name']}: {a.nx}x{a.ny} single domain, {a.bubbles} seeded bubbles R 25-40, "
-                        f"power-law liquid n=0.6 K=0.1, density ratio 1000, float32 arithmetic, "
+                        f"power-law liquid n=0.6 K=0.1, density ratio 1000, float32 arithmetic with the "
+                        f"phase field, the gbar level, their stencils and the bulk chemical potential in float64, "
                         + ("state: gbar level float64 + 8 deviations float32, C float64, tau float32 (tau_h = 1/2)"
                            if a.storage == 0 else
                            "state: gbar level float64 + momentum float32 + 6 float16 pair moments, C float64, "
@@ -267,6 +282,13 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(variant, a.nx, a.ny, a.storage)},
     }
+    vpu = measured_for(MEASURED_VALU, "instr_per_update", variant, a.nx, a.ny, a.storage)
+    if vpu is not None:
+        ceiling = VALU_ISSUE_PEAK / vpu / 1e6
+        out["roofline"]["valu"] = {"instr_per_update": vpu, "issue_peak_per_s": VALU_ISSUE_PEAK,
+                                   "ceiling_mlups": round(ceiling, 1), "frac": round(mlups / ceiling, 4)}
+    else:
+        out["roofline"]["valu"] = None
     del s
     torch.cuda.empty_cache()
     copy_gbs = copy_bandwidth(torch)

@@ -363,9 +363,10 @@ int32_t pflbm_init_fields(pflbm_ctx* c, int32_t k, const double* C, const double
 static hipError_t launch_one(pflbm_ctx* c, int par) {
     const CaseDev* cases = dev_case(c, 0);
     const TileDev* tiles = reinterpret_cast<const TileDev*>(c->ws + c->L.tiles_off);
-    bool impl = false;
-    for (const auto& p : c->prm) impl = impl || p.tau_iterations > 0;
-    const int form = (c->prm[0].storage == 1 ? 2 : (c->prm[0].store_h ? 1 : 0)) + (impl ? 3 : 0);
+    // the extended kernel instances when any case needs one of their features
+    bool ext = false;
+    for (const auto& p : c->prm) ext = ext || p.tau_iterations > 0 || p.hforce_cd || p.open_x;
+    const int form = (c->prm[0].storage == 1 ? 2 : (c->prm[0].store_h ? 1 : 0)) + (ext ? 3 : 0);
     return launch_step(c->variant, c->prm[0].n_h, form, cases, tiles, c->ntiles, par, c->stream);
 }
 

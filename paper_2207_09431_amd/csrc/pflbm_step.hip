@@ -123,7 +123,7 @@ __device__ __forceinline__ int region_node(int n, int rows, int& rx, int& ry) {
     return ry * W + rx;
 }
 
-template <int TX, int TY, int NH, bool SH, bool F16, int NT, bool IMPL>
+template <int TX, int TY, int NH, bool SH, bool F16, int NT, bool EXT>
 __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ cases,
                                                   const TileDev* __restrict__ tiles, int ntiles, int par) {
     constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
@@ -169,10 +169,12 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
     _Float16* Qout = cd.Q[par ^ 1];
     const float qinv = cd.qinv, qscale = cd.qscale;
     const int tid = threadIdx.x;
-    // open x (velocity inlet at x = 0, outflow at x = nx-1): stencil ghosts
-    // mirror in x like the walls' rows, and the boundary columns are
-    // completed in phase D
-    const bool openx = cd.openx != 0;
+    // open x (velocity inlet at x = 0, outflow at x = nx-1; extended
+    // instances): stencil ghosts mirror in x like the walls' rows, and the
+    // boundary columns are completed in phase D
+    const bool openx = EXT && cd.openx != 0;
+    // tiles whose regions reach beyond an open end (uniform per work-group)
+    const bool xedge = openx && (x0 < 3 || x0 + TX + 3 > nx);
 
     // ---------------- phase A: C_i and rho on R3
     // All global loads of phases A and B are issued here, phase A's first, so
@@ -353,7 +355,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const int gyr = y0 - 1 + ry;
         if (gyr < 0 || gyr >= ny) continue;   // nodes beyond the walls are never sources
         // nor, with open x, nodes beyond the ends (their populations are replaced)
-        if (openx && (x0 - 1 + rx < 0 || x0 - 1 + rx >= nx)) continue;
+        if (xedge) {
+            if (x0 - 1 + rx < 0 || x0 - 1 + rx >= nx) continue;
+        }
         const int i2 = (ry + 1) * W2 + rx + 1;
         const int i3 = (ry + 2) * W3 + rx + 2;
 
@@ -461,9 +465,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const float pin = sqrtf(2.0f * (pxx * pxx + pyy * pyy + 2.0f * pxy * pxy));
         float tau = mixture_tau(cd, c[0], c[1], c3, fs * pin);
         // optional fixed-point passes of the implicit relation tau = tau(gdot(tau))
-        // (Sec. 2.3, Eq. (32)), started from the previous step's tau; a kernel
-        // instance of its own, so that the default path has no loop here
-        if (IMPL)
+        // (Sec. 2.3, Eq. (32)), started from the previous step's tau; only in
+        // the extended instances, so that the default path has no loop here
+        if (EXT)
             for (int it = 0; it < cd.tau_iters; ++it)
                 tau = mixture_tau(cd, c[0], c[1], c3, 4.5f * rcp((tau + 0.5f) * rho) * pin);
         const float om = rcp(tau + 0.5f);
@@ -496,9 +500,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const float ub = ux * bx + uy * by;
         const float r3 = 3.0f * rcp(rho);
         // The forcing's (e_a-u).grad C_i takes the mixed directional
-        // derivatives (the default) or, with hforce_cd, central differences:
-        // then e_a.grad C_i joins the terms affine in e_a.  One copy of the
-        // block per choice, selected by a uniform branch.
+        // derivatives (the default) or, with hforce_cd (extended instances),
+        // central differences: then e_a.grad C_i joins the terms affine in
+        // e_a.  One copy of the block per choice, selected by a uniform branch.
         auto hbar_block = [&](auto cd_tag) {
             constexpr bool HCD = decltype(cd_tag)::value;
 #pragma unroll
@@ -536,7 +540,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
                 sDif[i][idx] = dif[i];
             }
         };
-        if (cd.hcd) hbar_block(std::true_type{});
+        if (EXT && cd.hcd) hbar_block(std::true_type{});
         else hbar_block(std::false_type{});
         // tau is written for the tile's own nodes
         const int ox = rx - 1, oy = ry - 1;
@@ -581,6 +585,11 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
                 if (!bb[a] && Lat::ey[a] != 0) sv += Lat::ey[a] > 0 ? pg : -pg;
                 ds[a] = (float)sv;
                 dv[a] = sD[dir[a]][src[a]];
+                if constexpr (!WALL) {
+                    // interior tiles: the sums in the same pass (same order of additions)
+                    if (a > 0) ssum += Lat::w[a] * ds[a];
+                    dsum += dv[a];
+                }
             }
             // region index of the output node on R3
             const int j3 = (oy + 3) * W3 + ox + 3;
@@ -654,10 +663,12 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
                     }
                 }
             }
+            if constexpr (WALL) {
 #pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                if (a > 0 && !bb[a]) ssum += Lat::w[a] * ds[a];
-                dsum += dv[a];
+                for (int a = 0; a < 9; ++a) {
+                    if (a > 0 && !bb[a]) ssum += Lat::w[a] * ds[a];
+                    dsum += dv[a];
+                }
             }
             const float dnew = ssum + dsum;               // s(t+1) - s(y)
             gst(Pout, eo * 8u, sy0 + (double)dnew);
@@ -756,7 +767,10 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
 
 // Step variants selectable at run time: tile shape x phase-field count x
 // state form (compact float32, stored hbar float32, compact float16; each
-// without and with the fixed-point passes of the implicit tau).  A tile
+// plain and extended).  The extended instances add the fixed-point passes of
+// the implicit tau, central differences in the hbar forcing and open x ends;
+// the plain ones carry none of that code (each costs ~1 % even unexecuted,
+// measured).  A tile
 // shape whose LDS footprint exceeds the 160 KiB of a gfx950 CU for two phase
 // fields is offered for one phase field only.
 using StepFn = void (*)(const CaseDev*, const TileDev*, int, int);
@@ -780,6 +794,10 @@ static const StepVariant kVariants[] = {
     PFLBM_V2(64, 8, 512),
     PFLBM_V1(64, 16, 512),
     PFLBM_V1(64, 16, 1024),
+    // small tiles for small domains: more work-groups where 32 x 16 tiles
+    // leave most compute units idle (a 64 x 128 domain is 16 such tiles)
+    PFLBM_V2(16, 8, 128),
+    PFLBM_V2(16, 16, 256),
 };
 
 int step_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
