@@ -280,16 +280,25 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(const CaseDev* __restric
         acc[4].add(cg * ux);
         acc[5].add(cg * uy);
     }
-    __shared__ double sh[6][kBlock];
-    for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = acc[k].value();
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
-        __syncthreads();
+    // wavefront reduction: a butterfly over the 64 lanes (lane 0's sum, the
+    // one kept, is formed in the same order on every run), then one value per
+    // wave through LDS, added in wave order
+    constexpr int kWaves = kBlock / 64;
+    __shared__ double sh[6][kWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        double v = acc[k].value();
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+        if (lane == 0) sh[k][wave] = v;
     }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 6; ++k) partials[blockIdx.x * 6 + k] = sh[k][0];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double v = 0.0;
+        for (int w = 0; w < kWaves; ++w) v += sh[threadIdx.x][w];
+        partials[blockIdx.x * 6 + threadIdx.x] = v;
+    }
 }
 
 __global__ void reduce_final_kernel(const double* __restrict__ partials, int nblocks, double* __restrict__ out) {
