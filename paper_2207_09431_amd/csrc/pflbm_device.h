@@ -48,6 +48,7 @@ struct CaseDev {
     _Float16* Q[2];
     float qscale, qinv;
     float rho[3], nu[3], inu[3];   // inu = 1 / nu
+    float inuF[3], nuloF, nuhiF;  // inu with 0 for the power-law component; min, max of the other nu
     int plc;            // power-law component or -1
     int vm;             // variable mobility
     int tau_iters;      // fixed-point passes of the implicit tau (0: previous step's tau)
@@ -283,18 +284,18 @@ __device__ __forceinline__ float powerlaw_nu(const CaseDev& cd, float gdot) {
 // series share the stress and add their shear rates, which the layered flow
 // of Sec. 3.3 (Table 3) reproduces.
 __device__ __forceinline__ float mixture_tau(const CaseDev& cd, float c1, float c2, float c3, float gdot) {
-    float n0 = cd.nu[0], n1 = cd.nu[1], n2 = cd.nu[2];
-    float i0 = cd.inu[0], i1 = cd.inu[1], i2 = cd.inu[2];
+    // the components of fixed viscosity (their inverse weights precomputed,
+    // the power-law component's set to 0), then the power-law component
+    float q = fmaf(clip01(c1), cd.inuF[0], fmaf(clip01(c2), cd.inuF[1], clip01(c3) * cd.inuF[2]));
+    float lo = cd.nuloF, hi = cd.nuhiF;
     if (cd.plc >= 0) {
-        const float np = powerlaw_nu(cd, gdot), ip = rcp(np);
-        if (cd.plc == 0) { n0 = np; i0 = ip; }
-        else if (cd.plc == 1) { n1 = np; i1 = ip; }
-        else { n2 = np; i2 = ip; }
+        const float np = powerlaw_nu(cd, gdot);
+        const float cp = cd.plc == 0 ? c1 : (cd.plc == 1 ? c2 : c3);
+        q = fmaf(clip01(cp), rcp(np), q);
+        lo = fminf(lo, np);
+        hi = fmaxf(hi, np);
     }
-    const float q = fmaf(clip01(c1), i0, fmaf(clip01(c2), i1, clip01(c3) * i2));
-    float nu = rcp(q);   // q > 0: the limited C_k sum to at least 1/3
-    const float lo = fminf(n0, fminf(n1, n2)), hi = fmaxf(n0, fmaxf(n1, n2));
-    nu = fminf(fmaxf(nu, lo), hi);
+    const float nu = fminf(fmaxf(rcp(q), lo), hi);   // q > 0: the limited C_k sum to at least 1/3
     return 3.0f * nu;
 }
 

@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -305,6 +306,12 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
         d.qinv = 1.0f / kQScale;
         for (int j = 0; j < 3; ++j) { d.rho[j] = (float)p.rho[j]; d.drho[j] = p.rho[j]; d.nu[j] = (float)p.nu[j]; d.inu[j] = (float)(1.0 / p.nu[j]); }
         d.plc = p.powerlaw_comp;
+        d.nuloF = INFINITY;
+        d.nuhiF = 0.0f;
+        for (int j = 0; j < 3; ++j) {
+            d.inuF[j] = j == d.plc ? 0.0f : d.inu[j];
+            if (j != d.plc) { d.nuloF = std::min(d.nuloF, d.nu[j]); d.nuhiF = std::max(d.nuhiF, d.nu[j]); }
+        }
         d.vm = p.variable_mobility ? 1 : 0;
         d.tau_iters = p.tau_iterations;
         d.hcd = p.hforce_cd;

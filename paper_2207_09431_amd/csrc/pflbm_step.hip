@@ -70,18 +70,21 @@ __device__ __forceinline__ float edot(int ex, int ey, float vx, float vy) {
 // spaced 6e-8, which the 5/4-weighted stencil turns into derivative noise of
 // that size, a random walk of the component mass and a velocity error at the
 // bubble rims; the stencil is therefore taken in float64 and rounded once.
+// Returns four times the derivatives (q_a = 4 d_a f, exact scaling) so that
+// each takes three float64 operations; the callers fold the 1/4 into their
+// coefficients, and the gradient is the true one.
 template <int W>
-__device__ __forceinline__ void md_all_d(const double* f, int i, float d[9], float& gx, float& gy) {
-    d[0] = 0.0f;
-    const double fc = -0.75 * f[i];
+__device__ __forceinline__ void md_all_d4(const double* f, int i, float q[9], float& gx, float& gy) {
+    q[0] = 0.0f;
+    const double m3 = -3.0 * f[i];
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
         const int o = Lat::ey[a] * W + Lat::ex[a];
-        d[a] = (float)fma(0.25, fma(5.0, f[i + o], -f[i + 2 * o]) - f[i - o], fc);
+        q[a] = (float)((fma(5.0, f[i + o], -f[i + 2 * o]) - f[i - o]) + m3);
     }
-    const float p5 = d[5] - d[7], p6 = d[6] - d[8];
-    gx = (1.0f / 3.0f) * (d[1] - d[3]) + (1.0f / 12.0f) * (p5 - p6);
-    gy = (1.0f / 3.0f) * (d[2] - d[4]) + (1.0f / 12.0f) * (p5 + p6);
+    const float p5 = q[5] - q[7], p6 = q[6] - q[8];
+    gx = (1.0f / 12.0f) * (q[1] - q[3]) + (1.0f / 48.0f) * (p5 - p6);
+    gy = (1.0f / 12.0f) * (q[2] - q[4]) + (1.0f / 48.0f) * (p5 + p6);
 }
 
 // Mixed directional derivatives along e_1..e_8 (mean of the central and the
@@ -414,7 +417,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         float drho[9], dc[2][9], mrx, mry, mcx[2] = {0.f, 0.f}, mcy[2] = {0.f, 0.f};
         md_all<W3>(sR, i3, drho, mrx, mry);
 #pragma unroll
-        for (int i = 0; i < NH; ++i) md_all_d<W3>(sCd[i], i3, dc[i], mcx[i], mcy[i]);
+        for (int i = 0; i < NH; ++i) md_all_d4<W3>(sCd[i], i3, dc[i], mcx[i], mcy[i]);   // dc = 4 d_a C_i
         if (NH == 1) {
 #pragma unroll
             for (int a = 0; a < 9; ++a) dc[1][a] = 0.0f;
@@ -462,7 +465,8 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         const float pxy = ne[5] - ne[6] + ne[7] - ne[8];
         // shear rate: D = -Pi / (2 (tau_prev + 1/2) rho c_s^4), gdot = sqrt(2 D:D)
         const float fs = 4.5f * rcp((tprev + 0.5f) * rho);
-        const float pin = sqrtf(2.0f * (pxx * pxx + pyy * pyy + 2.0f * pxy * pxy));
+        // hardware square root (1 ulp): the rate enters only the power law
+        const float pin = __builtin_amdgcn_sqrtf(2.0f * (pxx * pxx + pyy * pyy + 2.0f * pxy * pxy));
         float tau = mixture_tau(cd, c[0], c[1], c3, fs * pin);
         // optional fixed-point passes of the implicit relation tau = tau(gdot(tau))
         // (Sec. 2.3, Eq. (32)), started from the previous step's tau; only in
@@ -482,12 +486,13 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         if (NH == 2) T0 -= mu23 * um2;
         const float Z0 = om * m0, Zx = 3.0f * om * mx, Zy = 3.0f * om * my;
         const float cum = -kCs2 * umr;
+        const float mu13q = 0.25f * mu13, mu23q = 0.25f * mu23;   // dc holds 4 d_a C
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             const int ex = Lat::ex[a], ey = Lat::ey[a];
             const float K = fmaf(kCs2, drho[a], cum);
-            float t = fmaf(mu13, dc[0][a], T0 + edot(ex, ey, fbx, fby));
-            if (NH == 2) t = fmaf(mu23, dc[1][a], t);
+            float t = fmaf(mu13q, dc[0][a], T0 + edot(ex, ey, fbx, fby));
+            if (NH == 2) t = fmaf(mu23q, dc[1][a], t);
             const float br = fmaf(A[a], K + t, (Z0 + edot(ex, ey, Zx, Zy)) + t);
             sD[a][idx] = fmaf(Lat::w[a], br, fmaf(-om, ne[a], d[a]));
         }
@@ -523,17 +528,19 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
                     const float oc = oh * c[i];
 #pragma unroll
                     for (int a = 0; a < 9; ++a) {
-                        const float H = (HCD ? H0 : H0 + dc[i][a]) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
+                        const float H = (HCD ? H0 : fmaf(0.25f, dc[i][a], H0)) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
                         sH[i][a][idx] = Lat::w[a] * fmaf(A[a], oc + H, H);
                     }
                 } else {
                     // omega_h = 1: hbar* - w_a C = w_a A_a C + Gamma_a H_a
                     //   = w_a [H_a + A_a (C + H_a)],  H_a = -(e_a-u).X / 2 + forcing + Dif / 2
+                    // (the weight is applied here: applied by the receiver instead, inside
+                    // its sum, it triples the component mass drift, measured)
                     const float H0 = fmaf(0.5f, uX, fmaf(kk, ub, 0.5f * dif[i])) - umc;
                     const float Hx = fmaf(0.5f, Xx, kk * bx) - fgx, Hy = fmaf(0.5f, Xy, kk * by) - fgy;
 #pragma unroll
                     for (int a = 0; a < 9; ++a) {
-                        const float H = (HCD ? H0 : H0 + dc[i][a]) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
+                        const float H = (HCD ? H0 : fmaf(0.25f, dc[i][a], H0)) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
                         sH[i][a][idx] = Lat::w[a] * fmaf(A[a], c[i] + H, H);
                     }
                 }
