@@ -391,9 +391,11 @@ def many_bubbles_crop(nx: int = 2048, ny: int = 4096, count: int = 64, seed: int
     return case
 
 
-def batch_sweep(count_per_size: int = 16, seed: int = 4, sizes=((150, 300), (200, 400), (300, 600))):
+def batch_sweep(count_per_size: int = 16, seed: int = 4, sizes=((150, 300), (200, 400), (300, 600)),
+                density_ratio: float = 1000.0):
     """Uneven batch: `count_per_size` cases of each size, n ~ U[0.5,1.5],
-    Eo ~ U[1,100], density ratio 1000, d = width/5."""
+    Eo ~ U[1,100], d = width/5, density ratio 1000 unless given (the same
+    draws of n and Eo at any ratio)."""
     cases = []
     k = 0
     for (nx, ny) in sizes:
@@ -402,7 +404,7 @@ def batch_sweep(count_per_size: int = 16, seed: int = 4, sizes=((150, 300), (200
             k += 1
             n = 0.5 + n
             eo = 1.0 + 99.0 * eo
-            c = powerlaw_bubble(n=n, eo=eo, nx=nx, ny=ny, d=nx / 5.0)
+            c = powerlaw_bubble(n=n, eo=eo, nx=nx, ny=ny, d=nx / 5.0, density_ratio=density_ratio)
             c["name"] = f"batch_{nx}x{ny}_{k}"
             cases.append(c)
     return cases

@@ -146,6 +146,57 @@ def test_batch_48_matches_single_runs_and_oracle(torch):
         assert ru <= 1e-5 and rc <= 1e-5
 
 
+def test_batch_48_for_20000_steps_at_density_ratio_100(torch):
+    """The 48-case batch for the 20,000 steps of its configuration, replayed
+    as hipGraphs of 1,000 steps, at density ratio 100 (at 1000 every case of
+    this batch is non-finite by step 2,000, in line with the small bubbles of
+    the method as read at that ratio).  At 100 the cases with n below 1.27
+    stay finite; the strongly shear-thickening ones (n >= 1.29, all on the
+    two smaller lattices) do not, in the oracle as on the GPU.  Checks: the per-case
+    non-finite flags name exactly the cases whose fields hold a non-finite
+    value, every case with n < 1.27 is finite, and three finite cases, one of
+    each size, are bitwise equal to the same cases run one by one."""
+    from paper_2207_09431_amd.pflbm import Solver, PflbmError
+    cases = inputs.batch_sweep(density_ratio=100.0)
+    steps, every = 20000, 1000
+    b = Solver([c["params"] for c in cases])
+    for k, c in enumerate(cases):
+        b.init_fields(k, c["C"], c["u"], c["p"])
+    variant = b.autotune(steps=3)
+    b.set_graph(every)
+    for step in range(every, steps + 1, every):
+        b.step(every)
+    flagged = set()
+    try:
+        b.check_state()
+    except PflbmError as e:
+        assert e.status == -4
+        flagged = {k for k in range(len(cases)) if b.case_nonfinite(k)}
+    finite = set()
+    for k in range(len(cases)):
+        m = b.macroscopic(k)
+        if all(bool(torch.isfinite(m[f]).all()) for f in ("u", "p", "phi")):
+            finite.add(k)
+    print(f"variant {variant}; non-finite: {sorted((cases[k]['name'], round(cases[k]['params']['n'], 3)) for k in flagged)}",
+          flush=True)
+    assert flagged == set(range(len(cases))) - finite
+    assert all(k in finite for k in range(len(cases)) if cases[k]["params"]["n"] < 1.27)
+    names = b.variants()
+    for size in ("150x300", "200x400", "300x600"):
+        k = next(k for k in sorted(finite) if size in cases[k]["name"])
+        c = cases[k]
+        one = Solver(c["params"])
+        one.set_variant(names.index(variant))
+        one.init_fields(0, c["C"], c["u"], c["p"])
+        one.step(steps)
+        mb, m1 = b.macroscopic(k), one.macroscopic(0)
+        for f in ("u", "p", "phi"):
+            assert torch.equal(mb[f], m1[f]), (c["name"], f)
+        print(f"{c['name']}: batched graph replay == single run over {steps} steps", flush=True)
+        one.close()
+    b.close()
+
+
 @pytest.mark.parametrize("storage", [0, 1])
 def test_large_domain_10k_steps_at_density_ratio_100(torch, storage):
     """The 2048 x 4096 workload for the 10,000 steps of its configuration, at

@@ -176,6 +176,29 @@ def test_powerlaw_bubble(torch):
     compare(m, o)
 
 
+@pytest.mark.parametrize("n", [0.5, 0.8, 1.2])
+def test_config2_bubble_density_ratio_1000(torch, n):
+    """A d = 40 bubble in a power-law liquid (K = 0.1, nu in [1e-4, 1]) on a
+    200 x 400 lattice at density ratio 1000, Eo = 10, constant mobility, over
+    400 steps: the method as read (oracle and GPU alike) turns non-finite
+    between steps 500 and 1,000 at this size and ratio, and with variable
+    mobility within 500."""
+    case = inputs.powerlaw_bubble(n=n, eo=10.0, nx=200, ny=400, d=40.0)
+    s, m = gpu_run(case, 400)
+    compare(m, run_case(case, 400).macroscopic())
+
+
+@pytest.mark.parametrize("n", [0.8, 1.2])
+def test_config2_bubble_variable_mobility_density_ratio_100(torch, n):
+    """The same bubble with variable mobility (Sec. 2.1, Eq. (6)) and central
+    differences in the hbar forcing at density ratio 100, after the 2,000
+    steps of the float32 bound."""
+    case = inputs.powerlaw_bubble(n=n, eo=10.0, nx=200, ny=400, d=40.0, density_ratio=100.0)
+    case["params"].update(variable_mobility=1, hforce_cd=1)
+    s, m = gpu_run(case, 2000)
+    compare(m, run_case(case, 2000).macroscopic())
+
+
 @pytest.mark.parametrize("n", [0.5, 1.5])
 def test_powerlaw_channel(torch, n):
     """Rheology in a real shear flow: power-law liquid between the walls,
