@@ -61,3 +61,32 @@ def test_outflow_keeps_the_pressure_steady():
     p1 = o.macroscopic()["p"]
     drop = p0[:, 0].mean() - p0[:, -1].mean()
     assert np.abs(p1 - p0).max() < 1e-6 * drop / 500 * 500, (np.abs(p1 - p0).max(), drop)
+
+
+def test_inlet_and_outflow_keep_uniform_equilibrium_flow():
+    """Uniform flow u = (u_in, 0) at p = 0 with its equilibrium populations is
+    a fixed point of the interior scheme (no gradient, no force, and the
+    collision leaves an equilibrium unchanged).  The velocity inlet must
+    return exactly these populations at x = 0, including how its unknown
+    populations share the momentum (the odd part of the equilibrium, Sec.
+    3.2), and the convective outflow must return them at x = nx - 1; only the
+    walls disturb the flow, one row per step.  After 3 steps every population
+    of the rows at least 4 away from a wall, end columns included, equals its
+    initial value."""
+    nx, ny, u_in, steps = 24, 20, 0.1, 3
+    case = inputs.channel_inlet(1.0, nx=nx, ny=ny, u_in=u_in)
+    u = np.zeros((2, ny, nx))
+    u[0] = u_in
+    prm = dict(case["params"])
+    from oracle.pfo import Oracle
+    o = Oracle(prm)
+    o.init_fields(case["C"], u, np.zeros((ny, nx)))
+    g0, h0, _ = o.populations()
+    o.step(steps)
+    g1, h1, _ = o.populations()
+    rows = slice(steps + 1, ny - steps - 1)
+    scale = np.abs(g0).max()
+    assert np.abs(g1[:, rows, :] - g0[:, rows, :]).max() <= 1e-14 * scale
+    assert np.abs(h1[:, :, rows, :] - h0[:, :, rows, :]).max() <= 1e-14
+    # the walls did disturb the rows next to them (the check above is not vacuous)
+    assert np.abs(g1[:, 0, :] - g0[:, 0, :]).max() > 1e-6 * scale
