@@ -39,7 +39,10 @@ MUTATIONS = [
     ("linear mixture viscosity instead of the harmonic one",
      [("if (p->mix_linear) {", "if (!p->mix_linear) {")]),
     ("bounce-back returning the incoming direction",
-     [("sa = OPP[a];", "sa = a;")]),
+     [("if (sy < 0 || sy >= c->ny) return c->gpost[(size_t)OPP[a] * n",
+       "if (sy < 0 || sy >= c->ny) return c->gpost[(size_t)a * n"),
+      ("if (sy < 0 || sy >= c->ny) return c->hpost[((size_t)i * 9 + OPP[a]) * n",
+       "if (sy < 0 || sy >= c->ny) return c->hpost[((size_t)i * 9 + a) * n")]),
     ("second-order equilibrium term doubled",
      [("eu * eu / (2.0 * CS2 * CS2)", "eu * eu / (CS2 * CS2)")]),
     ("pressure term of the hbar forcing with the wrong sign",
@@ -60,7 +63,7 @@ MUTATIONS = [
      [("p->rho[0] * clip01(c1) + p->rho[1] * clip01(c2) + p->rho[2] * clip01(c3)",
        "p->rho[2] * clip01(c1) + p->rho[1] * clip01(c2) + p->rho[0] * clip01(c3)")]),
     ("streaming from the downstream neighbour",
-     [("wrapx(x - EX[a], nx); sa = a;", "wrapx(x + EX[a], nx); sa = a;")]),
+     [("int sy = y - EY[a], sx = x - EX[a], n = c->n;", "int sy = y - EY[a], sx = x + EX[a], n = c->n;")]),
     ("hbar relaxation rate 1/tau_h instead of 1/(tau_h + 1/2)",
      [("1.0 / (P->tau_h + 0.5)", "1.0 / P->tau_h")]),
     ("gradient part of the variable-mobility source dropped",
