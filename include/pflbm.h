@@ -56,14 +56,15 @@ typedef struct {
     double rho[3];             /* component densities, > 0 */
     double nu[3];              /* Newtonian kinematic viscosities nu_k = c_s^2 tau_k, > 0 */
     int32_t powerlaw_comp;     /* component whose viscosity is the power law (0..2), or -1 */
-    double K, n;               /* power law nu_P = K gdot^(n-1) (Sec. 2.3, Eq. (31)) */
+    double K, n;               /* power law nu_P = K gdot^(n-1) (Sec. 2.3, Eq. (31)); finite, > 0
+                                  when powerlaw_comp >= 0 */
     double nu_min, nu_max;     /* truncation of nu_P (Eq. (33)); 0 < nu_min <= nu_max */
     double sigma12, sigma13, sigma23; /* pairwise surface tensions (Sec. 2.1) */
     double Lambda;             /* six-fold term of the bulk free energy (Eq. (3)) */
-    double xi;                 /* interface thickness (Eq. (2)), > 0 */
-    double D0;                 /* mobility scale (Eq. (6)); xi/300 in the paper */
+    double xi;                 /* interface thickness (Eq. (2)), finite, > 0 */
+    double D0;                 /* mobility scale (Eq. (6)); xi/300 in the paper; finite, >= 0 */
     int32_t variable_mobility; /* 0: D_i = D0/Sigma_i, 1: D_i = D0/Sigma_i C_i (1-C_i) (Eq. (6)) */
-    double tau_h;              /* relaxation time of hbar (0.5 in the paper) */
+    double tau_h;              /* relaxation time of hbar (0.5 in the paper); finite, > 0 */
     double g;                  /* gravity: F_b = rho (fx, -g) (Eq. (12)) */
     double fx;                 /* horizontal body acceleration (0 in the paper's bubble runs) */
     int32_t storage;           /* 0: gbar deviations in float32; 1: float16 pair moments (see below) */

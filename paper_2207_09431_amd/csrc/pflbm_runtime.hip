@@ -85,10 +85,12 @@ bool valid_params(const pflbm_params& p) {
         if (!(p.rho[k] > 0.0) || !(p.nu[k] > 0.0) || !is_finite(p.rho[k]) || !is_finite(p.nu[k])) return false;
     if (p.powerlaw_comp < -1 || p.powerlaw_comp > 2) return false;
     if (p.powerlaw_comp >= 0) {
-        if (!(p.K > 0.0) || !is_finite(p.n) || !(p.nu_min > 0.0) || !(p.nu_min <= p.nu_max) || !is_finite(p.nu_max))
+        if (!(p.K > 0.0) || !is_finite(p.K) || !(p.n > 0.0) || !is_finite(p.n) || !(p.nu_min > 0.0) ||
+            !(p.nu_min <= p.nu_max) || !is_finite(p.nu_max))
             return false;
     }
     if (!(p.xi > 0.0) || !(p.D0 >= 0.0) || !(p.tau_h > 0.0)) return false;
+    if (!is_finite(p.xi) || !is_finite(p.D0) || !is_finite(p.tau_h)) return false;
     if (!is_finite(p.g) || !is_finite(p.fx) || !is_finite(p.Lambda)) return false;
     double S[3], ST;
     capillary(p, S, &ST);

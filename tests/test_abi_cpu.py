@@ -37,7 +37,10 @@ def test_workspace_bytes_valid_and_invalid(L):
     assert n > 9 * 2 * 4 * 64 * 128
     bad = [dict(prm, nx=4), dict(prm, n_h=3), dict(prm, rho=[0.0, 1.0, 1.0]), dict(prm, nu_min=2.0, nu_max=1.0,
            powerlaw_comp=2), dict(prm, tau_h=0.7, store_h=0), dict(prm, sigma23=1.0), dict(prm, xi=0.0),
-           dict(prm, tau_iterations=-1), dict(prm, tau_iterations=9)]
+           dict(prm, tau_iterations=-1), dict(prm, tau_iterations=9),
+           dict(prm, powerlaw_comp=2, n=0.0), dict(prm, powerlaw_comp=2, K=float("inf")),
+           dict(prm, xi=float("inf")), dict(prm, D0=float("nan")), dict(prm, tau_h=float("inf"), store_h=1),
+           dict(prm, hforce_cd=2), dict(prm, open_x=2), dict(prm, open_x=1, u_in=float("nan"))]
     for b in bad:
         assert pflbm.workspace_bytes([b]) == 0, b
     assert pflbm.workspace_bytes([dict(prm, tau_iterations=8)]) == n
