@@ -106,15 +106,6 @@ bool valid_params(const pflbm_params& p) {
     return true;
 }
 
-int smallest_tile_cells() {
-    int best = 1 << 30;
-    for (int v = 0; v < step_variant_count(); ++v) {
-        int tx, ty, nt;
-        if (step_variant_shape(v, 1, &tx, &ty, &nt) && tx * ty < best) best = tx * ty;
-    }
-    return best;
-}
-
 size_t max_tiles_for(const pflbm_params* cases, int n) {
     size_t worst = 0;
     for (int v = 0; v < step_variant_count(); ++v) {
@@ -135,7 +126,6 @@ bool make_layout(const pflbm_params* cases, int n, Layout* L) {
             cases[c].store_h != cases[0].store_h)
             return false;
     }
-    (void)smallest_tile_cells();
     size_t off = 0;
     L->cases_off = off;
     off = align_up(off + sizeof(CaseDev) * n, kAlign);
