@@ -37,6 +37,9 @@ MEASURED_VALU = {"source_sha256": "7c693a31d12376c4", "variant": "tile32x16_t512
                  "nx": 2048, "ny": 4096, "instr_per_update": 1002.1}
 VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 
+# steps per captured hipGraph in the graph-replay forms
+GRAPH_STEPS = 50
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -171,7 +174,7 @@ def small_configs(torch, Solver, inputs, steps, warmup):
     """The smaller configurations (cache-resident, bound by the latency of one
     tile's step): the 64 x 128 rising bubble, a 200 x 400 power-law bubble
     (d = 40) and the 256 x 512 three-component case; plain launches and
-    10-step hipGraph replay."""
+    hipGraph replay of GRAPH_STEPS steps (timed after two warm-up replays)."""
     out = {}
     for name, case in (("rising_bubble_64x128", inputs.rising_bubble_small()),
                        ("powerlaw_bubble_200x400", inputs.powerlaw_bubble(n=0.8, d=40.0)),
@@ -181,8 +184,8 @@ def small_configs(torch, Solver, inputs, steps, warmup):
         var = s.autotune(steps=3)
         cells = case["params"]["nx"] * case["params"]["ny"]
         ms, _ = timed_steps(torch, [s], steps, warmup)
-        s.set_graph(10)
-        ms_g, _ = timed_steps(torch, [s], steps - steps % 10, 10)
+        s.set_graph(GRAPH_STEPS)
+        ms_g, _ = timed_steps(torch, [s], max(GRAPH_STEPS, steps - steps % GRAPH_STEPS), 2 * GRAPH_STEPS)
         out[name] = {"mlups": round(cells / (ms * 1e-3) / 1e6, 1), "graph_mlups": round(cells / (ms_g * 1e-3) / 1e6, 1),
                      "ms_per_step": round(ms, 4), "variant": var, "bytes_per_update": s.bytes_per_update()}
         s.close()
@@ -199,8 +202,8 @@ def batch_forms(torch, Solver, inputs, steps, warmup):
         b.init_fields(k, c["C"], c["u"], c["p"])
     bvar = b.autotune(steps=3)
     ms_b, _ = timed_steps(torch, [b], steps, warmup)
-    b.set_graph(10)                                # the same launches replayed from a hipGraph
-    ms_g, _ = timed_steps(torch, [b], steps - steps % 10, 10)
+    b.set_graph(GRAPH_STEPS)                       # the same launches replayed from a hipGraph
+    ms_g, _ = timed_steps(torch, [b], max(GRAPH_STEPS, steps - steps % GRAPH_STEPS), 2 * GRAPH_STEPS)
     b.set_graph(0)
     singles = []
     for c in cases:
