@@ -90,6 +90,13 @@ typedef struct {
                                   extrapolation of p, and copies the neighbour's hbar.  Stencil
                                   ghosts beyond the ends mirror the end columns */
     double u_in;               /* inlet velocity (open_x = 1) */
+    int32_t mobility_flux;     /* form of the diffusion source div(D_i grad mu_i) (Sec. 2.2, Eq. (21)):
+                                  0 the product form D_i lap mu_i + grad D_i . grad mu_i, 1 the
+                                  conservative link form sum_a w_a (D_i(x) + D_i(x+e_a))
+                                  (mu_i(x+e_a) - mu_i(x)) / c_s^2, whose links cancel in pairs so
+                                  that the component totals keep no source of the method's own (with
+                                  variable mobility the product form does not, Eq. (6)); identical
+                                  to the product form in the continuum */
 } pflbm_params;
 
 /*
@@ -125,7 +132,7 @@ size_t pflbm_workspace_bytes(const pflbm_params* cases, int32_t ncases);
  * (nx or ny < 5, n_h not 1 or 2, rho_k <= 0, nu_k <= 0, nu_min <= 0 or
  * nu_min > nu_max, K <= 0 with a power-law component, xi <= 0, D0 < 0,
  * tau_h <= 0, a Sigma_i <= 0, store_h = 0 with tau_h != 0.5, storage not
- * 0 or 1, tau_iterations outside 0..8, hforce_cd or open_x not 0 or 1, a
+ * 0 or 1, tau_iterations outside 0..8, hforce_cd, open_x or mobility_flux not 0 or 1, a
  * non-finite u_in with open_x, nx rounded up to 64 times ny at or above 2^29
  * nodes);
  * UNSUPPORTED for storage = 1 with store_h = 1, or open_x with store_h = 1; WORKSPACE when the

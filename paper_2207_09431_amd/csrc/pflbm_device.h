@@ -55,6 +55,7 @@ struct CaseDev {
     int hcd;            // central differences for grad C_i in the hbar forcing
     int openx;          // velocity inlet at x = 0 and outflow at x = nx-1 (else x periodic)
     float u_in;         // inlet velocity
+    int mflux;          // conservative link form of the diffusion source
     float K, nexp, numin, numax;
     float sig12, sig13, sig23, lam;
     float Sig[3];

@@ -11,7 +11,8 @@ int step_variant_count();
 bool step_variant_shape(int v, int nh, int* tx, int* ty, int* nt);
 // state forms of the step: compact float32, stored hbar float32, compact
 // float16 (0..2), and the same extended (3..5) with the fixed-point passes of
-// the implicit tau, central differences in the hbar forcing and open x ends
+// the implicit tau, central differences in the hbar forcing, open x ends and
+// the link form of the diffusion source
 constexpr int kStepForms = 6;
 hipError_t launch_step(int v, int nh, int form, const CaseDev* cases, const TileDev* tiles, int ntiles, int par,
                        hipStream_t stream);

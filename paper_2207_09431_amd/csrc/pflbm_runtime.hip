@@ -103,6 +103,7 @@ bool valid_params(const pflbm_params& p) {
     if (p.hforce_cd != 0 && p.hforce_cd != 1) return false;
     if (p.open_x != 0 && p.open_x != 1) return false;
     if (p.open_x && !is_finite(p.u_in)) return false;
+    if (p.mobility_flux != 0 && p.mobility_flux != 1) return false;
     return true;
 }
 
@@ -309,6 +310,7 @@ int32_t pflbm_create(const pflbm_params* cases, int32_t ncases, void* d_workspac
         d.hcd = p.hforce_cd;
         d.openx = p.open_x;
         d.u_in = (float)p.u_in;
+        d.mflux = p.mobility_flux;
         d.K = (float)p.K; d.nexp = (float)p.n; d.numin = (float)p.nu_min; d.numax = (float)p.nu_max;
         d.sig12 = (float)p.sigma12; d.sig13 = (float)p.sigma13; d.sig23 = (float)p.sigma23; d.lam = (float)p.Lambda;
         double S[3], ST;
@@ -364,7 +366,7 @@ static hipError_t launch_one(pflbm_ctx* c, int par) {
     const TileDev* tiles = reinterpret_cast<const TileDev*>(c->ws + c->L.tiles_off);
     // the extended kernel instances when any case needs one of their features
     bool ext = false;
-    for (const auto& p : c->prm) ext = ext || p.tau_iterations > 0 || p.hforce_cd || p.open_x;
+    for (const auto& p : c->prm) ext = ext || p.tau_iterations > 0 || p.hforce_cd || p.open_x || p.mobility_flux;
     const int form = (c->prm[0].storage == 1 ? 2 : (c->prm[0].store_h ? 1 : 0)) + (ext ? 3 : 0);
     return launch_step(c->variant, c->prm[0].n_h, form, cases, tiles, c->ntiles, par, c->stream);
 }

@@ -9,7 +9,8 @@
 //      chemical potentials (Eq. (5)), the velocity and pressure moments
 //      (Eqs. (23), (24) with the 1/2 factor on u.grad rho) from the gbar state;
 //   C  on the 1-node halo: grad p, grad mu, lap mu, the diffusion source of
-//      Eq. (21), mixed directional derivatives of rho and C_i, the shear rate
+//      Eq. (21) (product form, or in the extended instances optionally the
+//      conservative link form), mixed directional derivatives of rho and C_i, the shear rate
 //      from the non-equilibrium second moment with the previous tau
 //      (Eqs. (25)-(29)), the truncated power-law viscosity (Eqs. (31), (33))
 //      mixed harmonically across the interface into tau (optionally with
@@ -399,7 +400,24 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
             float mx, my;
             cd_grad<W2>(sMu[i], i2, mx, my);
             const float lapmu = cd_lap<W2>(sMu[i], i2);
-            if (cd.vm) {
+            if (EXT && cd.mflux) {
+                // conservative link form (extended instances):
+                //   sum_a w_a (D(x) + D(x+e_a)) (mu(x+e_a) - mu(x)) / c_s^2,
+                // D = mob C (1 - C) with C limited to [0, 1], or mob when constant
+                auto shape = [&](int j) {
+                    if (!cd.vm) return 1.0f;
+                    const float q = clip01(sC[i][j]);
+                    return q - q * q;
+                };
+                const float m0 = shape(i3), u0 = sMu[i][i2];
+                float acc = 0.0f;
+#pragma unroll
+                for (int a = 1; a < 9; ++a) {
+                    const int o2 = Lat::ey[a] * W2 + Lat::ex[a], o3 = Lat::ey[a] * W3 + Lat::ex[a];
+                    acc = fmaf(Lat::w[a] * (m0 + shape(i3 + o3)), sMu[i][i2 + o2] - u0, acc);
+                }
+                dif[i] = cd.mob[i] * (3.0f * acc);
+            } else if (cd.vm) {
                 // grad of C_i - C_i^2 with C_i limited to [0, 1]
                 auto sf = [&](int j) { const float q = clip01(sC[i][j]); return q - q * q; };
                 const float e1 = sf(i3 + 1) - sf(i3 - 1), e2 = sf(i3 + W3) - sf(i3 - W3);
@@ -775,7 +793,8 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
 // Step variants selectable at run time: tile shape x phase-field count x
 // state form (compact float32, stored hbar float32, compact float16; each
 // plain and extended).  The extended instances add the fixed-point passes of
-// the implicit tau, central differences in the hbar forcing and open x ends;
+// the implicit tau, central differences in the hbar forcing, open x ends and
+// the link form of the diffusion source;
 // the plain ones carry none of that code (each costs ~1 % even unexecuted,
 // measured).  A tile
 // shape whose LDS footprint exceeds the 160 KiB of a gfx950 CU for two phase

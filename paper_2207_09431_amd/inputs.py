@@ -115,7 +115,7 @@ def default_params(nx: int, ny: int) -> dict:
         sigma12=1e-3, sigma13=1e-3, sigma23=1e-3, Lambda=0.0,
         xi=4.0, D0=4.0 / 300.0, variable_mobility=1,
         tau_h=0.5, g=0.0, fx=0.0,
-        storage=0, store_h=0, hforce_cd=0, open_x=0, u_in=0.0,
+        storage=0, store_h=0, hforce_cd=0, open_x=0, u_in=0.0, mobility_flux=0,
     )
 
 

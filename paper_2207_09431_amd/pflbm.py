@@ -46,7 +46,7 @@ class Params(ct.Structure):
         ("g", ct.c_double), ("fx", ct.c_double),
         ("storage", ct.c_int32), ("store_h", ct.c_int32),
         ("tau_iterations", ct.c_int32), ("hforce_cd", ct.c_int32),
-        ("open_x", ct.c_int32), ("u_in", ct.c_double),
+        ("open_x", ct.c_int32), ("u_in", ct.c_double), ("mobility_flux", ct.c_int32),
     ]
 
 

@@ -100,6 +100,8 @@ MUTATIONS = [
      [("g[5] += 0.5 * ry;\n            g[8] -= 0.5 * ry;", "g[5] -= 0.5 * ry;\n            g[8] += 0.5 * ry;")]),
     ("inlet unknowns without the odd part of the equilibrium",
      [("if (unknown[a]) g[a] = g[OPP[a]] + gbar_eq(&m, a) - gbar_eq(&m, OPP[a]);", "if (unknown[a]) g[a] = g[OPP[a]];")]),
+    ("link-form diffusion source with the node's own mobility at both ends of every link",
+     [("s += W[a] * (m0 + m1) * (at(mi,", "s += W[a] * (m0 + m0) * (at(mi,")]),
     ("mass above one half counts cells instead of summing C",
      [("if (cg > 0.5) mh += cg;", "if (cg > 0.5) mh += 1.0;")]),
     ("mean velocity weighted by 1 instead of C",

@@ -4,8 +4,9 @@ The step kernel is instantiated per tile variant, phase-field count n_h and
 state form (compact float32, stored hbar, float16 storage; each with and
 without the fixed-point tau passes of Sec. 2.3, Eq. (32)), and selects at run
 time the stencil of the hbar forcing (central differences, used with variable
-mobility, or mixed directional differences) and the x boundaries (periodic, or
-a velocity inlet and an outflow, Sec. 3.2).  Each instance
+mobility, or mixed directional differences), the form of the diffusion source
+(product or conservative link form, Eq. (21)) and the x boundaries (periodic,
+or a velocity inlet and an outflow, Sec. 3.2).  Each instance
 that the autotuner can pick runs a ragged domain (neither side a multiple of
 any tile) and is compared element by element with the oracle (relative L2
 and max norm), and the variants of one form are bitwise equal to each other.
@@ -31,6 +32,8 @@ FORMS = [
     ("float16_implicit_tau", dict(storage=1, tau_iterations=3), 1e-3),
     ("float32_variable_mobility_central_hbar_forcing", dict(variable_mobility=1, hforce_cd=1), 1e-5),
     ("float16_variable_mobility_central_hbar_forcing", dict(storage=1, variable_mobility=1, hforce_cd=1), 1e-3),
+    ("float32_variable_mobility_link_form", dict(variable_mobility=1, hforce_cd=1, mobility_flux=1), 1e-5),
+    ("float16_variable_mobility_link_form", dict(storage=1, variable_mobility=1, hforce_cd=1, mobility_flux=1), 1e-3),
     ("float32_open_x", dict(open_x=1, u_in=0.01), 1e-5),
     ("float16_open_x", dict(storage=1, open_x=1, u_in=0.01), 1e-3),
 ]

@@ -39,10 +39,11 @@ def slab(x):
     return out
 
 
-def one_step_change(d0, variable):
+def one_step_change(d0, variable, flux=False):
     prm = dict(nx=NX, ny=NY, n_h=1, rho=[1.0, 1.0, 1.0], nu=[1 / 6] * 3, powerlaw_comp=-1, K=0.1, n=1.0,
                nu_min=1e-4, nu_max=1.0, sigma12=SIGMA, sigma13=SIGMA, sigma23=SIGMA, Lambda=0.0, xi=XI,
-               D0=d0, variable_mobility=int(variable), tau_h=0.5, g=0.0, fx=0.0, storage=0, store_h=0)
+               D0=d0, variable_mobility=int(variable), tau_h=0.5, g=0.0, fx=0.0, storage=0, store_h=0,
+               mobility_flux=int(flux))
     c0 = slab(np.arange(NX, dtype=np.float64))
     o = Oracle(prm)
     o.init_fields(np.repeat(c0[None, None, :], NY, axis=1), None, None)
@@ -75,9 +76,11 @@ def smooth(a):
     return 5.0 / 6.0 * a + (np.roll(a, 1) + np.roll(a, -1)) / 12.0
 
 
-@pytest.mark.parametrize("variable, tol", [(False, 0.02), (True, 0.03)])
-def test_diffusion_source_matches_continuum_operator(variable, tol):
-    obs = one_step_change(D0, variable) - one_step_change(0.0, variable)
+@pytest.mark.parametrize("variable, flux, tol", [(False, False, 0.02), (True, False, 0.03),
+                                                  (False, True, 0.02), (True, True, 0.03)])
+def test_diffusion_source_matches_continuum_operator(variable, flux, tol):
+    """Product form and conservative link form alike."""
+    obs = one_step_change(D0, variable, flux) - one_step_change(0.0, variable, flux)
     ref = smooth(continuum_source(variable))
     err = np.abs(obs - ref).max() / np.abs(ref).max()
     assert err < tol, err
