@@ -40,7 +40,8 @@ def test_workspace_bytes_valid_and_invalid(L):
            dict(prm, tau_iterations=-1), dict(prm, tau_iterations=9),
            dict(prm, powerlaw_comp=2, n=0.0), dict(prm, powerlaw_comp=2, K=float("inf")),
            dict(prm, xi=float("inf")), dict(prm, D0=float("nan")), dict(prm, tau_h=float("inf"), store_h=1),
-           dict(prm, hforce_cd=2), dict(prm, open_x=2), dict(prm, open_x=1, u_in=float("nan"))]
+           dict(prm, hforce_cd=2), dict(prm, open_x=2), dict(prm, open_x=1, u_in=float("nan")),
+           dict(prm, mobility_flux=2)]
     for b in bad:
         assert pflbm.workspace_bytes([b]) == 0, b
     assert pflbm.workspace_bytes([dict(prm, tau_iterations=8)]) == n
