@@ -3,6 +3,7 @@ together in one batched solver on the GPU, with the drag post-processing of
 Sec. 4.1.
 
     python -m paper_2207_09431_amd.sweep [--ratio 200] [--cases 3,4,5,6] [--steps 60000] [--scale 2]
+        [--mobility constant|variable] [--source product|link] [--hbar-forcing mixed|central]
 
 prints one JSON object per case.  The terminal velocity is read as the
 largest sampled mean rise velocity (Eq. (44)) before the bubble comes within
@@ -57,6 +58,10 @@ def run_sweep(cases: list, max_steps: int, every: int = 1000, solver_factory=Sol
     for i, c in enumerate(cases):
         res = {"case": c["name"], "steps": samples[i][-1][0] if samples[i] else 0, "end": end[i],
                "samples": samples[i], "report": None}
+        if samples[i]:
+            # the largest sampled rise velocity, also for a case that ended non-finite
+            j = max(range(len(samples[i])), key=lambda q: samples[i][q][1][5])
+            res["max_vy"], res["max_vy_step"] = samples[i][j][1][5], samples[i][j][0]
         if samples[i] and not end[i].startswith("nonfinite"):
             k = max(range(len(samples[i])), key=lambda j: samples[i][j][1][5])
             if 0 < k < len(samples[i]) - 1:
@@ -95,6 +100,12 @@ def main(argv=None) -> int:
                     help="sampling interval on the 200 x 400 lattice (default 1,000); multiplied by scale^2")
     ap.add_argument("--scale", type=int, default=1,
                     help="lattice f times finer than 200 x 400 at the same Re, Eo and Mo")
+    ap.add_argument("--mobility", choices=("constant", "variable"), default="constant",
+                    help="D_i constant or proportional to C_i (1 - C_i) (Eq. (6))")
+    ap.add_argument("--source", choices=("product", "link"), default="product",
+                    help="diffusion source of Eq. (21) in the product or the conservative link form")
+    ap.add_argument("--hbar-forcing", choices=("mixed", "central"), default="mixed",
+                    help="stencil of (e_a - u).grad C_i in the hbar forcing (variable mobility needs central)")
     a = ap.parse_args(argv)
     # at fixed Re, Eo and Mo lattice velocities scale by 1/f and lengths by f,
     # so the same physical time takes f^2 times the steps
@@ -102,6 +113,10 @@ def main(argv=None) -> int:
     steps = (60000 if a.steps is None else a.steps) * f2
     every = (1000 if a.every is None else a.every) * f2
     all_cases = inputs.shear_thinning_sweep(density_ratio=a.ratio, scale=a.scale)
+    over = dict(variable_mobility=int(a.mobility == "variable"), mobility_flux=int(a.source == "link"),
+                hforce_cd=int(a.hbar_forcing == "central"))
+    for c in all_cases:
+        c["params"] = dict(c["params"], **over)
     pick = [int(x) - 1 for x in a.cases.split(",")]
     for r in run_sweep([all_cases[i] for i in pick], steps, every):
         r = dict(r)
