@@ -90,6 +90,21 @@ def run_sweep(cases: list, max_steps: int, every: int = 1000, solver_factory=Sol
     return out
 
 
+def table5_cases(ratio: float, scale: int = 1, mobility: str = "constant", source: str = "product",
+                 hbar_forcing: str = "mixed") -> list:
+    """The six bubbles of Table 5 at the given density ratio and lattice
+    scale, with the mobility (constant or variable, Eq. (6)), the form of the
+    diffusion source (product or conservative link form, Eq. (21)) and the
+    stencil of the hbar forcing (mixed or central differences) set in every
+    case's parameter block."""
+    cases = inputs.shear_thinning_sweep(density_ratio=ratio, scale=scale)
+    over = dict(variable_mobility=int(mobility == "variable"), mobility_flux=int(source == "link"),
+                hforce_cd=int(hbar_forcing == "central"))
+    for c in cases:
+        c["params"] = dict(c["params"], **over)
+    return cases
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--ratio", type=float, default=200.0, help="liquid/gas density ratio (the paper's is 800)")
@@ -112,11 +127,7 @@ def main(argv=None) -> int:
     f2 = a.scale * a.scale
     steps = (60000 if a.steps is None else a.steps) * f2
     every = (1000 if a.every is None else a.every) * f2
-    all_cases = inputs.shear_thinning_sweep(density_ratio=a.ratio, scale=a.scale)
-    over = dict(variable_mobility=int(a.mobility == "variable"), mobility_flux=int(a.source == "link"),
-                hforce_cd=int(a.hbar_forcing == "central"))
-    for c in all_cases:
-        c["params"] = dict(c["params"], **over)
+    all_cases = table5_cases(a.ratio, a.scale, a.mobility, a.source, a.hbar_forcing)
     pick = [int(x) - 1 for x in a.cases.split(",")]
     for r in run_sweep([all_cases[i] for i in pick], steps, every):
         r = dict(r)

@@ -83,3 +83,25 @@ def test_peak_endings_and_report(monkeypatch):
     assert b["end"] == "nonfinite by step 3000" and b["report"] is None
     assert c["end"] == "max_steps" and c["report"] is None and "peak_step" not in c   # peak at the last sample
     assert d["end"] == "top_wall" and d["steps"] < 10000
+
+
+@pytest.mark.parametrize("mobility, source, forcing", [("constant", "product", "mixed"),
+                                                       ("variable", "link", "central")])
+def test_table5_cases_carry_the_chosen_method_switches(mobility, source, forcing):
+    cases = sweep.table5_cases(100.0, 1, mobility, source, forcing)
+    assert len(cases) == 6
+    for c in cases:
+        p = c["params"]
+        assert p["variable_mobility"] == (mobility == "variable")
+        assert p["mobility_flux"] == (source == "link")
+        assert p["hforce_cd"] == (forcing == "central")
+        assert p["rho"][2] / p["rho"][0] == pytest.approx(100.0)
+
+
+def test_reports_the_largest_sampled_velocity_also_for_a_diverged_case():
+    """A case that turns non-finite still reports its largest sampled rise
+    velocity and the step it was sampled at."""
+    Scripted.scripts = [lambda t: None if t >= 4000 else 1e-6 * t]
+    out = sweep.run_sweep([case("c0")], 10000, 1000, solver_factory=Scripted)
+    assert out[0]["end"] == "nonfinite by step 4000"
+    assert out[0]["max_vy"] == pytest.approx(3e-3) and out[0]["max_vy_step"] == 3000
