@@ -59,6 +59,21 @@ def test_channel_parity_while_developing(Solver, n):
     assert np.abs(m["phi"]).max() == 0.0
 
 
+@pytest.mark.parametrize("n", [0.5, 1.5])
+def test_channel_parity_float16_storage(Solver, n):
+    """The same in the float16 storage form, to its 1e-3 bound."""
+    case = inputs.channel_inlet(n)
+    s = Solver(dict(case["params"], storage=1))
+    s.init_fields(0, case["C"])
+    s.step(2000)
+    m = fields(s)
+    o = run_case(case, 2000).macroscopic()
+    ru, rp = rel_l2(m["u"], o["u"]), rel_l2(m["p"], o["p"])
+    mu, _ = max_norms(m, o)
+    print(f"float16 rel-L2 u {ru:.2e} p {rp:.2e} max u {mu:.2e}", flush=True)
+    assert ru <= 1e-3 and mu <= 1e-2
+
+
 def test_channel_matches_table2(Solver):
     ref = json.load(open(GOLDEN))
     cases = [inputs.channel_inlet(n) for n in ref["n"]]
