@@ -252,12 +252,13 @@ const char* pflbm_variant_name(const pflbm_ctx* ctx, int32_t index);
 int32_t pflbm_set_variant(pflbm_ctx* ctx, int32_t index);
 
 /*
- * Times every variant on the current state for `steps` launches each and
+ * Times every variant on the current state for `steps` launches each, in
+ * two passes over the variants (each variant's faster pass counts), and
  * selects the fastest for pflbm_step.  The state is left unchanged (each
  * timed launch recomputes the same step into the spare buffer).  `best`
  * receives the chosen index; `ms_per_variant` (NULL or pflbm_num_variants
- * floats) receives the mean milliseconds per step, -1 for a variant that does
- * not apply.  Synchronises the stream.  Errors: STATE before init_fields;
+ * floats) receives the mean milliseconds per step of that pass, -1 for a
+ * variant that does not apply.  Synchronises the stream.  Errors: STATE before init_fields;
  * NONFINITE (after tuning) when a case is flagged non-finite.
  */
 int32_t pflbm_autotune(pflbm_ctx* ctx, int32_t steps, int32_t* best, float* ms_per_variant);
