@@ -10,8 +10,9 @@
 //      (Eqs. (23), (24) with the 1/2 factor on u.grad rho) from the gbar state;
 //   C  on the 1-node halo: grad p, grad mu, lap mu, the diffusion source of
 //      Eq. (21) (product form, or in the extended instances optionally the
-//      conservative link form), mixed directional derivatives of rho and C_i, the shear rate
-//      from the non-equilibrium second moment with the previous tau
+//      conservative link form), mixed directional derivatives of rho and
+//      C_i, the shear rate from the non-equilibrium second moment with the
+//      previous tau
 //      (Eqs. (25)-(29)), the truncated power-law viscosity (Eqs. (31), (33))
 //      mixed harmonically across the interface into tau (optionally with
 //      fixed-point passes of Eq. (32)) and the post-collision populations of
@@ -67,7 +68,8 @@ __device__ __forceinline__ float edot(int ex, int ey, float vx, float vy) {
     const float t = ex > 0 ? vx : -vx;
     return ey > 0 ? t + vy : t - vy;
 }
-// The same from the float64 phase field: near C = 1 the float32 copy is
+// The mixed directional derivatives of md_all (below) from the float64
+// phase field: near C = 1 the float32 copy is
 // spaced 6e-8, which the 5/4-weighted stencil turns into derivative noise of
 // that size, a random walk of the component mass and a velocity error at the
 // bubble rims; the stencil is therefore taken in float64 and rounded once.
@@ -107,10 +109,11 @@ __device__ __forceinline__ void md_all(const float* f, int i, float d[9], float&
 }
 
 // Thread-to-node order on a region of width TX + 2h: the TX middle columns
-// first, a row of TX nodes per TX threads, so that every half-wave (32 lanes)
-// reads 32 consecutive LDS words of one row and the stencil reads of the
-// other regions (row pitches TX + 2..6) meet no bank conflict; the 2h edge
-// columns of every row follow.  Returns the region-linear index.
+// first, a row of TX nodes per TX threads, so that (for TX = 32) every
+// half-wave (32 lanes) reads 32 consecutive LDS words of one row and the
+// stencil reads of the other regions (row pitches TX + 2..6) meet no bank
+// conflict; the 2h edge columns of every row follow.  Returns the
+// region-linear index.
 template <int TX, int H>
 __device__ __forceinline__ int region_node(int n, int rows, int& rx, int& ry) {
     constexpr int W = TX + 2 * H;
