@@ -82,3 +82,25 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         pflbm.workspace_bytes([prm])
     with pytest.raises(RuntimeError, match="missing"):
         pflbm.Solver(prm)
+
+
+def test_params_layout_matches_the_header(tmp_path):
+    """The binding's ctypes mirror of pflbm_params has the header's size and
+    every field at the header's offset (a C program compiled against
+    include/pflbm.h prints them)."""
+    import ctypes as ct
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    names = [f for f, _ in pflbm.Params._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"pflbm.h\"\nint main(void) {\n"
+                   "  printf(\"%zu\\n\", sizeof(pflbm_params));\n"
+                   + "".join(f"  printf(\"%zu\\n\", offsetof(pflbm_params, {n}));\n" for n in names)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert out[0] == ct.sizeof(pflbm.Params)
+    assert out[1:] == [getattr(pflbm.Params, n).offset for n in names]
