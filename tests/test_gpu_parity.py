@@ -179,6 +179,23 @@ def test_variable_mobility_link_form_2000_steps(torch):
         assert abs(g[0] / r[0] - 1) < 1e-8 and abs(r[0] / r0[0] - 1) < 1e-12
 
 
+@pytest.mark.parametrize("steps", [0, 100])
+def test_export_populations_match_oracle(torch, steps):
+    """pflbm_export_populations: the 9 gbar planes (w_a s + d_a from the
+    level and the deviations), C and tau of the small rising bubble equal the
+    oracle's populations after initialisation (Eqs. (16), (20)) and after 100
+    steps, to the float32 state's precision."""
+    case = inputs.rising_bubble_small()
+    s, _ = gpu_run(case, steps)
+    out = s.export_populations(0).cpu().numpy().astype(np.float64)
+    o = run_case(case, steps)
+    g, h, tau = o.populations()
+    C = o.macroscopic()["phi"]
+    eg, ec, et = rel_l2(out[:9], g), rel_l2(out[9:10], C), rel_l2(out[10], tau)
+    print(f"steps {steps}: rel-L2 gbar {eg:.2e} C {ec:.2e} tau {et:.2e}", flush=True)
+    assert eg <= 1e-6 and ec <= 1e-6 and et <= 1e-6
+
+
 def test_crop_2000_steps(torch):
     """The 256 x 512 window of the large seeded domain (density ratio 1000,
     power-law liquid) after the 2,000 steps of the float32 bound."""
