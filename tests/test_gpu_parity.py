@@ -350,6 +350,11 @@ def test_degenerate_calls(torch):
         assert e.value.status == -1
     # all outputs NULL is a no-op
     assert lib().pflbm_macroscopic(s._h, 0, None, None, None, None) == 0
+    # an unknown variant has no name; -1 restores the default variant; the
+    # context reports the caller's stream
+    assert lib().pflbm_variant_name(s._h, len(s.variants())) is None
+    assert lib().pflbm_set_variant(s._h, -1) == 0
+    assert (lib().pflbm_stream(s._h) or 0) == s.stream.cuda_stream
     s.step(2)
     assert np.isfinite(s.macroscopic(0)["u"].cpu().numpy()).all()
 
