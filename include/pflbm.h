@@ -259,7 +259,9 @@ int32_t pflbm_set_variant(pflbm_ctx* ctx, int32_t index);
  * receives the chosen index; `ms_per_variant` (NULL or pflbm_num_variants
  * floats) receives the mean milliseconds per step of that pass, -1 for a
  * variant that does not apply.  Synchronises the stream.  Errors: STATE before init_fields;
- * NONFINITE (after tuning) when a case is flagged non-finite.
+ * NONFINITE (after tuning) when a case is flagged non-finite; DEVICE when a
+ * launch or event fails, after which the variant in use before the call is
+ * selected again.
  */
 int32_t pflbm_autotune(pflbm_ctx* ctx, int32_t steps, int32_t* best, float* ms_per_variant);
 

@@ -441,6 +441,7 @@ int32_t pflbm_autotune(pflbm_ctx* c, int32_t steps, int32_t* best, float* ms_per
     float bestms = 0.f;
     int32_t st = PFLBM_OK;
     const int nv = step_variant_count();
+    const int prev = c->variant;
     std::vector<float> best_ms(nv, -1.0f);
     // two passes over the variants, each variant's faster one counting: the
     // first variants timed would otherwise meet the GPU still ramping up
@@ -471,7 +472,10 @@ int32_t pflbm_autotune(pflbm_ctx* c, int32_t steps, int32_t* best, float* ms_per
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (st != PFLBM_OK) return st;
+    if (st != PFLBM_OK) {
+        (void)build_tiles(c, prev);   // best effort: leave the variant the call found
+        return st;
+    }
     if (best) *best = bestv;
     st = build_tiles(c, bestv);
     if (st == PFLBM_OK && any_nonfinite(c)) st = PFLBM_ERR_NONFINITE;
