@@ -8,6 +8,7 @@ GPU) every call raises.
 from __future__ import annotations
 
 import ctypes as ct
+import json
 import os
 
 import numpy as np
@@ -137,6 +138,14 @@ def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
 
 
+def _read_json(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
 class Solver:
     """A set of domains advanced together on one GPU (one case = plain path)."""
 
@@ -241,6 +250,10 @@ class Solver:
         return buf
 
     def set_state(self, buf):
+        # the ABI copies device to device: take only a contiguous byte tensor on this solver's GPU
+        if (buf.device != self.device and not (buf.is_cuda and self.device.index is None)) or \
+                buf.dtype != self.torch.uint8 or not buf.is_contiguous():
+            raise PflbmError("pflbm_set_state: expected a contiguous uint8 tensor on " + str(self.device), -1)
         _check("pflbm_set_state", lib().pflbm_set_state(self._h, ct.c_void_p(buf.data_ptr()), buf.numel()))
 
     def export_populations(self, case_id=0):
@@ -265,7 +278,6 @@ class Solver:
         """Pick the fastest tile variant for these cases on this GPU.  With a
         `cache` path (JSON), a previous choice for the same case shapes is
         reused instead of timing again.  Returns the chosen variant name."""
-        import json
         key = None
         names = self.variants()
         if cache is not None:
@@ -273,10 +285,7 @@ class Solver:
             dev = torch.cuda.get_device_properties(self.device).name
             key = json.dumps([dev, [(p["nx"], p["ny"], p["n_h"], p.get("store_h", 0), p.get("storage", 0))
                                     for p in self.params]])
-            try:
-                table = json.load(open(cache))
-            except (OSError, ValueError):
-                table = {}
+            table = _read_json(cache)
             if key in table and table[key] in names:
                 self.set_variant(names.index(table[key]))
                 return table[key]
@@ -287,10 +296,7 @@ class Solver:
         self.tuning = {names[i]: float(ms[i]) for i in range(n) if ms[i] >= 0}
         name = names[best.value]
         if cache is not None:
-            try:
-                table = json.load(open(cache))
-            except (OSError, ValueError):
-                table = {}
+            table = _read_json(cache)
             table[key] = name
             with open(cache, "w") as f:
                 json.dump(table, f, indent=1)

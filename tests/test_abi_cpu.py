@@ -104,3 +104,15 @@ def test_params_layout_matches_the_header(tmp_path):
     out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert out[0] == ct.sizeof(pflbm.Params)
     assert out[1:] == [getattr(pflbm.Params, n).offset for n in names]
+
+
+def test_set_state_rejects_host_and_non_byte_tensors():
+    """The state copy is device to device: a host tensor, or one of another
+    dtype, is refused before any ABI call (no GPU needed for the check)."""
+    import torch
+    s = pflbm.Solver.__new__(pflbm.Solver)
+    s.torch, s.device, s._h = torch, torch.device("cuda:0"), None
+    for buf in (torch.zeros(16, dtype=torch.uint8), torch.zeros(4, dtype=torch.float32)):
+        with pytest.raises(pflbm.PflbmError) as e:
+            s.set_state(buf)
+        assert e.value.status == -1
