@@ -825,10 +825,14 @@ static const StepVariant kVariants[] = {
     PFLBM_V1(64, 16, 1024),
     // small tiles for small domains: more work-groups where 32 x 16 tiles
     // leave most compute units idle (a 64 x 128 domain is 16 such tiles,
-    // 128 tiles of 8 x 8)
+    // 128 tiles of 8 x 8); with 256 threads every phase of an 8 x 8 tile,
+    // and all but the first of a 16 x 8 tile, takes one pass, which
+    // shortens the step of a lone tile
     PFLBM_V2(16, 8, 128),
     PFLBM_V2(16, 16, 256),
     PFLBM_V2(8, 8, 128),
+    PFLBM_V2(8, 8, 256),
+    PFLBM_V2(16, 8, 256),
 };
 
 int step_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
