@@ -40,7 +40,7 @@ typedef enum {
     PFLBM_ERR_DEVICE = -3,        /* a HIP call failed */
     PFLBM_ERR_NONFINITE = -4,     /* non-finite input, or the state became non-finite */
     PFLBM_ERR_STATE = -5,         /* call out of order (e.g. step before init_fields) */
-    PFLBM_ERR_UNSUPPORTED = -6    /* valid request this build does not provide */
+    PFLBM_ERR_UNSUPPORTED = -6    /* valid request the library does not provide */
 } pflbm_status;
 
 typedef struct pflbm_ctx pflbm_ctx;

@@ -647,7 +647,7 @@ const char* pflbm_status_string(int32_t s) {
         case PFLBM_ERR_DEVICE: return "HIP device error";
         case PFLBM_ERR_NONFINITE: return "non-finite value";
         case PFLBM_ERR_STATE: return "call out of order";
-        case PFLBM_ERR_UNSUPPORTED: return "unsupported in this build";
+        case PFLBM_ERR_UNSUPPORTED: return "unsupported by the library";
         default: return "unknown status";
     }
 }
