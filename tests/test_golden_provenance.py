@@ -1,8 +1,8 @@
 """The stored oracle records in tests/golden come from the oracle as it
-stands: the first sample of the shear-thinning terminal-velocity record
-(1,000 steps of the 200 x 400 case) is recomputed here and must agree to
-rounding.  (The other record's first sample needs 8,000 steps of a
-128 x 512 case, minutes on the CPU; its script is the same shape.)"""
+stands: the first sample of each shear-thinning record (1,000 steps of a
+200 x 400 Table 5 case) is recomputed here and must agree to rounding.
+(The other record's first sample needs 8,000 steps of a 128 x 512 case,
+minutes on the CPU; its script is the same shape.)"""
 import json
 import os
 
@@ -14,13 +14,15 @@ from paper_2207_09431_amd import inputs
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def test_sweep_record_first_sample_recomputes():
-    with open(os.path.join(GOLDEN, "sweep_case4_terminal.json")) as f:
+@pytest.mark.parametrize("record, index, over", [("sweep_case4_terminal.json", 3, {}),
+                                                  ("sweep_case1_cd_terminal.json", 0, {"hforce_cd": 1})])
+def test_sweep_record_first_sample_recomputes(record, index, over):
+    with open(os.path.join(GOLDEN, record)) as f:
         rec = json.load(f)
     first = rec["samples"][0]
-    case = inputs.shear_thinning_sweep(density_ratio=200.0)[3]
-    assert rec["case"] == case["name"]
-    o = Oracle(case["params"])
+    case = inputs.shear_thinning_sweep(density_ratio=200.0)[index]
+    assert rec["case"] == case["name"] + ("_hforce_cd" if over else "")
+    o = Oracle(dict(case["params"], **over))
     o.init_fields(case["C"], case["u"], case["p"])
     o.step(first["step"])
     mass, _, _, yc, _, uy = o.centroid(0)

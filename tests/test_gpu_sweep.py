@@ -65,3 +65,35 @@ def test_shear_thinning_terminal_velocity_matches_oracle(torch, storage):
     print(f"worst V_y deviation {worst:.2e}, y_c {worst_y:.2e}; terminal gpu {r['report']['U']:.6e} oracle {peak_ref:.6e}", flush=True)
     assert worst < 5e-3 and worst_y < 0.05
     assert abs(r["report"]["U"] / peak_ref - 1) < 5e-3
+
+
+def test_largest_eo_bubble_with_central_hbar_forcing_matches_oracle(torch):
+    """Table 5's case 1 (n = 0.5, Eo 479, the most deformed bubble) at
+    density ratio 200 with central differences in the hbar forcing, with
+    which it rises to a peak: the batched sweep's samples of the mean rise
+    velocity and centroid against the oracle's (stored in tests/golden by
+    make_sweep_case1_cd.py, which calls only the oracle) every 1,000 steps
+    from 2,000 to 14,000, and the peak (at step 11,000) within 0.5 %."""
+    import json
+    import os
+    from paper_2207_09431_amd.sweep import run_sweep
+    with open(os.path.join(os.path.dirname(__file__), "golden", "sweep_case1_cd_terminal.json")) as f:
+        ref = json.load(f)["samples"]
+    case = inputs.shear_thinning_sweep(density_ratio=200.0)[0]
+    case["params"] = dict(case["params"], hforce_cd=1)
+    print(f"case {case['name']} hforce_cd 1", flush=True)
+    r = run_sweep([case], ref[-1]["step"], 1000)[0]
+    got = {step: diag for step, diag in r["samples"]}
+    worst, worst_y = 0.0, 0.0
+    for row in ref:
+        if row["step"] < 2000:
+            continue
+        v, y = got[row["step"]][5], got[row["step"]][3]
+        worst = max(worst, abs(v / row["V_y"] - 1))
+        worst_y = max(worst_y, abs(y - row["y_c"]))
+    peak = max(ref, key=lambda row: row["V_y"])
+    print(f"worst V_y deviation {worst:.2e}, y_c {worst_y:.2e}; peak gpu {r['report']['U']:.6e} at {r.get('peak_step')} "
+          f"oracle {peak['V_y']:.6e} at {peak['step']}", flush=True)
+    assert worst < 5e-3 and worst_y < 0.05
+    assert r.get("peak_step") == peak["step"]
+    assert abs(r["report"]["U"] / peak["V_y"] - 1) < 5e-3
