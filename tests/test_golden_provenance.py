@@ -14,14 +14,18 @@ from paper_2207_09431_amd import inputs
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-@pytest.mark.parametrize("record, index, over", [("sweep_case4_terminal.json", 3, {}),
-                                                  ("sweep_case1_cd_terminal.json", 0, {"hforce_cd": 1})])
-def test_sweep_record_first_sample_recomputes(record, index, over):
+@pytest.mark.parametrize("record, ratio, index, suffix, over", [
+    ("sweep_case4_terminal.json", 200.0, 3, "", {}),
+    ("sweep_case1_cd_terminal.json", 200.0, 0, "_hforce_cd", {"hforce_cd": 1}),
+    ("sweep_case4_vm_link.json", 100.0, 3, "_variable_link",
+     {"variable_mobility": 1, "mobility_flux": 1, "hforce_cd": 1})])
+def test_sweep_record_first_sample_recomputes(record, ratio, index, suffix, over):
     with open(os.path.join(GOLDEN, record)) as f:
         rec = json.load(f)
     first = rec["samples"][0]
-    case = inputs.shear_thinning_sweep(density_ratio=200.0)[index]
-    assert rec["case"] == case["name"] + ("_hforce_cd" if over else "")
+    case = inputs.shear_thinning_sweep(density_ratio=ratio)[index]
+    assert rec["case"] == case["name"] + suffix
+    assert rec.get("switches", over) == over
     o = Oracle(dict(case["params"], **over))
     o.init_fields(case["C"], case["u"], case["p"])
     o.step(first["step"])

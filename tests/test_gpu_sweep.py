@@ -97,3 +97,34 @@ def test_largest_eo_bubble_with_central_hbar_forcing_matches_oracle(torch):
     assert worst < 5e-3 and worst_y < 0.05
     assert r.get("peak_step") == peak["step"]
     assert abs(r["report"]["U"] / peak["V_y"] - 1) < 5e-3
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_variable_mobility_link_form_bubble_matches_oracle(torch, storage):
+    """Table 5's case 4 at density ratio 100 with variable mobility (Eq. (6)),
+    the diffusion source in the conservative link form and central
+    differences in the hbar forcing: the batched sweep's samples of the mean
+    rise velocity, centroid and component total against the oracle's
+    (stored in tests/golden by make_sweep_case4_vm.py, which calls only the
+    oracle) every 1,000 steps from 2,000 to 20,000; in both storage forms."""
+    import json
+    import os
+    from paper_2207_09431_amd.sweep import run_sweep
+    with open(os.path.join(os.path.dirname(__file__), "golden", "sweep_case4_vm_link.json")) as f:
+        rec = json.load(f)
+    ref = rec["samples"]
+    case = inputs.shear_thinning_sweep(density_ratio=100.0)[3]
+    case["params"] = dict(case["params"], storage=storage, **rec["switches"])
+    print(f"case {case['name']} {rec['switches']} storage {storage}", flush=True)
+    r = run_sweep([case], ref[-1]["step"], 1000)[0]
+    got = {step: diag for step, diag in r["samples"]}
+    worst, worst_y, worst_m = 0.0, 0.0, 0.0
+    for row in ref:
+        if row["step"] < 2000:
+            continue
+        g = got[row["step"]]
+        worst = max(worst, abs(g[5] / row["V_y"] - 1))
+        worst_y = max(worst_y, abs(g[3] - row["y_c"]))
+        worst_m = max(worst_m, abs(g[0] / row["mass"] - 1))
+    print(f"worst V_y deviation {worst:.2e}, y_c {worst_y:.2e}, total {worst_m:.2e}", flush=True)
+    assert worst < 5e-3 and worst_y < 0.05 and worst_m < 1e-7
