@@ -7,8 +7,9 @@ with the mixed directional form the update amplifies oblique modes wherever
 the mobility vanishes (the oracle pin in test_oracle_mobility.py), and
 variable mobility vanishes in every bulk phase.  Constant mobility keeps the
 default (mixed) form.  GPU parity of both forms with the oracle over 2,000
-steps is in test_gpu_parity.py and test_gpu_instances.py; this file records
-what the two mobilities do over 50,000 steps, as properties.
+steps is in test_gpu_parity.py and test_gpu_instances.py, of the link form
+over 10,000 steps at the end of this file; the rest records what the two
+mobilities do over 50,000 steps, as properties.
 """
 import numpy as np
 import pytest
@@ -88,3 +89,43 @@ def test_variable_mobility_link_form_conserves_totals(record):
     for comp in (0, 1):
         assert abs(link[-1][comp][0] / link[0][comp][0] - 1) < 1e-7, comp
         assert abs(prod[-1][comp][0] / prod[0][comp][0] - 1) > 1e-3, comp
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_variable_mobility_link_form_matches_oracle_over_10000_steps(storage):
+    """The Sec. 3.1 bubble and droplet with variable mobility, the link form
+    of the diffusion source and central differences in the hbar forcing,
+    against the oracle's samples (stored in tests/golden by
+    make_droplet_vm_link.py, which calls only the oracle) every 1,000 steps
+    to 10,000, for both components: rise velocity within 0.5 % of the
+    component's largest, centroid within 0.05, total within 1e-7 and mass
+    above C = 1/2 within 1e-4; in both storage forms."""
+    import json
+    import os
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2207_09431_amd.pflbm import Solver
+    with open(os.path.join(os.path.dirname(__file__), "golden", "droplet_vm_link.json")) as f:
+        rec = json.load(f)
+    case = inputs.bubble_droplet(variable_mobility=1, hforce_cd=1)
+    prm = dict(case["params"], storage=storage, **rec["switches"])
+    print(f"case {case['name']} {rec['switches']} storage {storage}", flush=True)
+    s = Solver(prm)
+    s.init_fields(0, case["C"], case.get("u"), case.get("p"))
+    worst = {"V_y": 0.0, "y_c": 0.0, "mass": 0.0, "mass_above_half": 0.0}
+    vmax = {k: max(abs(r[f"c{k + 1}"]["V_y"]) for r in rec["samples"]) for k in (0, 1)}
+    done = 0
+    for row in rec["samples"]:
+        s.step(row["step"] - done)
+        done = row["step"]
+        for k in (0, 1):
+            mass, above, _, yc, _, vy = s.bubble_centroid_velocity(0, k)
+            ref = row[f"c{k + 1}"]
+            worst["V_y"] = max(worst["V_y"], abs(vy - ref["V_y"]) / vmax[k])
+            worst["y_c"] = max(worst["y_c"], abs(yc - ref["y_c"]))
+            worst["mass"] = max(worst["mass"], abs(mass / ref["mass"] - 1))
+            worst["mass_above_half"] = max(worst["mass_above_half"], abs(above / ref["mass_above_half"] - 1))
+    print("worst " + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()), flush=True)
+    assert worst["V_y"] < 5e-3 and worst["y_c"] < 0.05
+    assert worst["mass"] < 1e-7 and worst["mass_above_half"] < 1e-4
