@@ -7,9 +7,9 @@ with the mixed directional form the update amplifies oblique modes wherever
 the mobility vanishes (the oracle pin in test_oracle_mobility.py), and
 variable mobility vanishes in every bulk phase.  Constant mobility keeps the
 default (mixed) form.  GPU parity of both forms with the oracle over 2,000
-steps is in test_gpu_parity.py and test_gpu_instances.py, of the link form
-over 10,000 steps at the end of this file; the rest records what the two
-mobilities do over 50,000 steps, as properties.
+steps is in test_gpu_parity.py and test_gpu_instances.py, over 10,000 steps
+(the link form and constant mobility) at the end of this file; the rest
+records what the two mobilities do over 50,000 steps, as properties.
 """
 import numpy as np
 import pytest
@@ -92,23 +92,26 @@ def test_variable_mobility_link_form_conserves_totals(record):
 
 
 @pytest.mark.parametrize("storage", [0, 1])
-def test_variable_mobility_link_form_matches_oracle_over_10000_steps(storage):
-    """The Sec. 3.1 bubble and droplet with variable mobility, the link form
-    of the diffusion source and central differences in the hbar forcing,
-    against the oracle's samples (stored in tests/golden by
-    make_droplet_vm_link.py, which calls only the oracle) every 1,000 steps
-    to 10,000, for both components: rise velocity within 0.5 % of the
-    component's largest, centroid within 0.05, total within 1e-7 and mass
-    above C = 1/2 within 1e-4; in both storage forms."""
+@pytest.mark.parametrize("record", ["droplet_constant.json", "droplet_vm_link.json"])
+def test_bubble_droplet_matches_oracle_over_10000_steps(record, storage):
+    """The Sec. 3.1 bubble and droplet against the oracle's samples (stored
+    in tests/golden by make_droplet_records.py, which calls only the oracle)
+    every 1,000 steps to 10,000, for both components: with constant mobility
+    and the default hbar forcing (the plain kernel instance), and with
+    variable mobility, the link form of the diffusion source and central
+    differences in the hbar forcing (the extended instance).  Rise velocity
+    within 0.5 % of the component's largest, centroid within 0.05, total
+    within 1e-7 and mass above C = 1/2 within 1e-4; in both storage forms."""
     import json
     import os
     import torch
     if not torch.cuda.is_available():
         pytest.fail("no GPU visible")
     from paper_2207_09431_amd.pflbm import Solver
-    with open(os.path.join(os.path.dirname(__file__), "golden", "droplet_vm_link.json")) as f:
+    with open(os.path.join(os.path.dirname(__file__), "golden", record)) as f:
         rec = json.load(f)
-    case = inputs.bubble_droplet(variable_mobility=1, hforce_cd=1)
+    vm = rec["variable_mobility"]
+    case = inputs.bubble_droplet(variable_mobility=vm, hforce_cd=1 if vm else 0)
     prm = dict(case["params"], storage=storage, **rec["switches"])
     print(f"case {case['name']} {rec['switches']} storage {storage}", flush=True)
     s = Solver(prm)
