@@ -1,8 +1,11 @@
 """The shear-thinning bubbles of Table 5 (Sec. 4.3) on the GPU, batched, with
 the drag post-processing of Sec. 4.1.  At the paper's density ratio of 800
 every case becomes non-finite within 2,000 steps (as in the oracle); at 200
-cases 3-6 rise to a terminal velocity, which this test requires, and the
-report's Eo must be the input's (Eq. (40) on the measured diameter)."""
+cases 3-6 rise to a terminal velocity, which the first test requires, and
+the report's Eo must be the input's (Eq. (40) on the measured diameter).
+The others follow single cases against stored oracle samples over long
+runs: case 4 (both storage forms), case 1 with central differences in the
+hbar forcing, and case 4 with variable mobility in the link form."""
 import pytest
 
 from paper_2207_09431_amd import inputs
