@@ -6,8 +6,9 @@ arithmetic.  A "step" is one time step of the whole domain (collision,
 streaming, bounce-back, phase-field update); the timed region covers exactly
 `--steps` steps with the state resident in HBM.  The tile variant is chosen by
 the autotuner before timing.  Prints one JSON line; the "forms" object adds
-the batched 48-case sweep (batched vs one by one), the stored-hbar form and
-the float16 storage form.
+the batched 48-case sweep (batched vs one by one), the stored-hbar form,
+the float16 storage form, the three-component system on the same domain and
+the smaller configurations.
 """
 import argparse
 import json
@@ -25,15 +26,15 @@ HBM_PEAK_GBS = 8000.0
 # read for a 512 MiB device copy (x 1.9999 and x 1.0).  Valid only for the kernel
 # sources they were taken on (sha256 prefix of pflbm_step.hip + pflbm_device.h)
 # and the same tile variant; otherwise the bench reports null.
-MEASURED_TRAFFIC = {"source_sha256": "05ec2fd2c555962a", "variant": "tile32x16_t512",
-                    "nx": 2048, "ny": 4096, "bytes_per_launch": 900.0e6}
+MEASURED_TRAFFIC = {"source_sha256": "758de792fac2b12a", "variant": "tile32x16_t512",
+                    "nx": 2048, "ny": 4096, "bytes_per_launch": 899.3e6}
 
 # VALU instructions per lattice update of the same kernel (rocprofv3
 # SQ_INSTS_VALU / SQ_WAVES: one wave per 64 updates, halo work included),
 # under the same conditions as MEASURED_TRAFFIC.  The VALU issue ceiling of
 # MI355X without packed float32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz =
 # 39.3 T lane-instructions/s.
-MEASURED_VALU = {"source_sha256": "05ec2fd2c555962a", "variant": "tile32x16_t512",
+MEASURED_VALU = {"source_sha256": "758de792fac2b12a", "variant": "tile32x16_t512",
                  "nx": 2048, "ny": 4096, "instr_per_update": 1002.1}
 VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 
@@ -317,6 +318,18 @@ def main():
                                     "variant": qvar, "bytes_per_update": sq.bytes_per_update(),
                                     "achieved_GBs": round(sq.bytes_per_update() * cells / (ms_q * 1e-3) / 1e9, 1)}
         del sq
+        torch.cuda.empty_cache()
+        # the three-component system (two phase fields) on the same domain
+        tc = inputs.three_component(nx=a.nx, ny=a.ny)
+        st = Solver(tc["params"], device="cuda:0")
+        st.init_fields(0, tc["C"], tc.get("u"), tc.get("p"))
+        tvar = st.autotune(steps=5)
+        ms_t, _ = timed_steps(torch, [st], max(20, a.steps // 4), 5)
+        forms["three_component"] = {"mlups": round(cells / (ms_t * 1e-3) / 1e6, 1), "ms_per_step": round(ms_t, 4),
+                                    "variant": tvar, "bytes_per_update": st.bytes_per_update(),
+                                    "achieved_GBs": round(st.bytes_per_update() * cells / (ms_t * 1e-3) / 1e9, 1)}
+        del st
+        torch.cuda.empty_cache()
         forms["small_configs"] = small_configs(torch, Solver, inputs, max(100, a.steps), 20)
         out["forms"] = forms
     if not a.no_cpu_baseline:

@@ -442,6 +442,15 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         if (NH == 1) {
 #pragma unroll
             for (int a = 0; a < 9; ++a) dc[1][a] = 0.0f;
+        } else {
+            // two phase fields: each d_a C_i waits in that component's own hbar
+            // planes at this node (free once the parked values were read) and is
+            // read back where it is used, so that the collision does not hold
+            // both sets of nine in registers
+#pragma unroll
+            for (int i = 0; i < NH; ++i)
+#pragma unroll
+                for (int a = 1; a < 9; ++a) sH[i][a][idx] = dc[i][a];
         }
 
         // force, equilibrium and the non-equilibrium part.  With
@@ -512,8 +521,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
         for (int a = 0; a < 9; ++a) {
             const int ex = Lat::ex[a], ey = Lat::ey[a];
             const float K = fmaf(kCs2, drho[a], cum);
-            float t = fmaf(mu13q, dc[0][a], T0 + edot(ex, ey, fbx, fby));
-            if (NH == 2) t = fmaf(mu23q, dc[1][a], t);
+            const float dc0 = NH == 2 ? (a == 0 ? 0.0f : sH[0][a][idx]) : dc[0][a];
+            float t = fmaf(mu13q, dc0, T0 + edot(ex, ey, fbx, fby));
+            if (NH == 2) t = fmaf(mu23q, a == 0 ? 0.0f : sH[1][a][idx], t);
             const float br = fmaf(A[a], K + t, (Z0 + edot(ex, ey, Zx, Zy)) + t);
             sD[a][idx] = fmaf(Lat::w[a], br, fmaf(-om, ne[a], d[a]));
         }
@@ -549,7 +559,8 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
                     const float oc = oh * c[i];
 #pragma unroll
                     for (int a = 0; a < 9; ++a) {
-                        const float H = (HCD ? H0 : fmaf(0.25f, dc[i][a], H0)) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
+                        const float dca = NH == 2 ? (a == 0 ? 0.0f : sH[i][a][idx]) : dc[i][a];
+                        const float H = (HCD ? H0 : fmaf(0.25f, dca, H0)) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
                         sH[i][a][idx] = Lat::w[a] * fmaf(A[a], oc + H, H);
                     }
                 } else {
@@ -561,7 +572,8 @@ __global__ __launch_bounds__(NT) void step_kernel(const CaseDev* __restrict__ ca
                     const float Hx = fmaf(0.5f, Xx, kk * bx) - fgx, Hy = fmaf(0.5f, Xy, kk * by) - fgy;
 #pragma unroll
                     for (int a = 0; a < 9; ++a) {
-                        const float H = (HCD ? H0 : fmaf(0.25f, dc[i][a], H0)) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
+                        const float dca = NH == 2 ? (a == 0 ? 0.0f : sH[i][a][idx]) : dc[i][a];
+                        const float H = (HCD ? H0 : fmaf(0.25f, dca, H0)) - edot(Lat::ex[a], Lat::ey[a], Hx, Hy);
                         sH[i][a][idx] = Lat::w[a] * fmaf(A[a], c[i] + H, H);
                     }
                 }
