@@ -26,15 +26,15 @@ HBM_PEAK_GBS = 8000.0
 # read for a 512 MiB device copy (x 1.9999 and x 1.0).  Valid only for the kernel
 # sources they were taken on (sha256 prefix of pflbm_step.hip + pflbm_device.h)
 # and the same tile variant; otherwise the bench reports null.
-MEASURED_TRAFFIC = {"source_sha256": "758de792fac2b12a", "variant": "tile32x16_t512",
-                    "nx": 2048, "ny": 4096, "bytes_per_launch": 899.3e6}
+MEASURED_TRAFFIC = {"source_sha256": "4f41d287dbabd5e7", "variant": "tile32x16_t512",
+                    "nx": 2048, "ny": 4096, "bytes_per_launch": 899.1e6}
 
 # VALU instructions per lattice update of the same kernel (rocprofv3
 # SQ_INSTS_VALU / SQ_WAVES: one wave per 64 updates, halo work included),
 # under the same conditions as MEASURED_TRAFFIC.  The VALU issue ceiling of
 # MI355X without packed float32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz =
 # 39.3 T lane-instructions/s.
-MEASURED_VALU = {"source_sha256": "758de792fac2b12a", "variant": "tile32x16_t512",
+MEASURED_VALU = {"source_sha256": "4f41d287dbabd5e7", "variant": "tile32x16_t512",
                  "nx": 2048, "ny": 4096, "instr_per_update": 1002.1}
 VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 

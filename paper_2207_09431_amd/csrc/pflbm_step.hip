@@ -832,6 +832,9 @@ static const StepVariant kVariants[] = {
     PFLBM_V2(32, 16, 512),
     PFLBM_V2(32, 16, 256),
     PFLBM_V2(32, 8, 256),
+    // one pass per phase but the first for a 32 x 8 tile: with two phase
+    // fields (67 KB of LDS, two work-groups per CU) the fastest on large domains
+    PFLBM_V2(32, 8, 512),
     PFLBM_V2(64, 8, 512),
     PFLBM_V1(64, 16, 512),
     PFLBM_V1(64, 16, 1024),
